@@ -1,0 +1,73 @@
+/*
+ * Cell2Fire reference oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded FP64 CPU implementation of the fire-growth
+ * hot path of Cell2Fire (Pais et al., "Cell2Fire: A Cell Based Forest Fire
+ * Growth Model"): FBP rate of spread per cell (Sections 2.3 and 3.7), the
+ * elliptical directional rate of eq. (1), and the synchronous send/receive
+ * message loop of Algorithm 1 stepped minute by minute (Sections 3.1 and
+ * 3.4).  Only the test-suite, the smoke check and the benchmark's CPU
+ * baseline may call it; the simulator library never does.  It shares no
+ * code, header or table with the simulator.
+ *
+ * All entry points return 0 on success and a negative value on bad input.
+ */
+#ifndef CELL2FIRE_ORACLE_H
+#define CELL2FIRE_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Horn 3x3 gradient numerators with edge replication (east, north). */
+int oracle_horn(int32_t rows, int32_t cols, const int16_t* elev, int32_t* gx, int32_t* gn);
+
+/* One FBP evaluation for a single fuel at explicit slope (percent) and
+ * upslope azimuth (degrees clockwise from north).  out[0..9] =
+ * HROS, BROS, FROS, LB, RAZ (deg), ISI, WSV, BE, RSI, WSE. */
+int oracle_fbp_point(int32_t fuel, double ffmc, double bui, double ws_kmh, double wd_from_deg,
+                     double slope_pct, double upslope_az_deg, double pc_pct, double curing_pct,
+                     double* out);
+
+/* Directional rates of eq. (1) on the 8 centre-to-centre axes
+ * (E, NE, N, NW, W, SW, S, SE) for the given head/back/flank rates and RAZ. */
+void oracle_axis_ros(double hros, double bros, double fros, double raz_deg, double* out8);
+
+/* Per-cell FBP field for one (scenario, period, replication).  Any output
+ * pointer may be NULL.  hros/bros/fros include the replication's noise
+ * multiplier; x8 is the unquantised axis rate, xu8 = x8 + u (the value that is
+ * floored) and q8 the integer axis rate.  raz is in degrees. */
+int oracle_eval_ros(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
+                    const int16_t* elev, double pc_pct, double curing_pct,
+                    int32_t n_scen, int32_t n_wperiods, const float* weather,
+                    int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
+                    int32_t rounding, double* hros, double* bros, double* fros, double* lb,
+                    double* raz, double* x8, double* xu8, int32_t* q8);
+
+/* Monte-Carlo fire simulation.  Replication r uses global index
+ * rep_offset + r in every random draw.  Outputs may be NULL.
+ * scar/arrival_* are [reps][rows*cols]; burn_count [rows*cols] is
+ * overwritten; burned_cells, ignition_cell, scenario_out are [reps].
+ * n_override entries (rep, period, cell) -> q[8] replace computed integer
+ * axis rates (data only; used to replay another implementation's rounding).
+ * stats (may be NULL) receives [ignitions, burning-cell-minutes, fbp evals]. */
+int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
+                    const int16_t* elev, double pc_pct, double curing_pct,
+                    int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,
+                    int32_t reps, int32_t rep_offset, int32_t n_periods, uint64_t seed,
+                    double sigma, double threshold, int32_t rounding,
+                    int32_t ignition_mode, int32_t ignition_cell,
+                    int32_t scenario_mode, int32_t scenario_fixed,
+                    int32_t n_override, const int32_t* override_key, const int32_t* override_q,
+                    uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
+                    uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
+                    int32_t* scenario_out, int64_t* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

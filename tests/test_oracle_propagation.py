@@ -1,0 +1,352 @@
+"""Pins for the oracle's minute-stepping propagation (Algorithm 1).
+
+Independent references used here:
+  * scipy's Dijkstra: with one fuel, flat ground and constant weather every
+    hop along axis k costs ceil(D_k / q_k) minutes from any departure time, so
+    arrival minutes are shortest-path lengths;
+  * a closed form for the zero-wind octagon;
+  * a time-dependent Dijkstra written in this file (label setting with the
+    per-period closed-form walk of the axis progress), run on random
+    heterogeneous grids with changing weather, noise, stochastic rounding,
+    short periods and ignition thresholds.
+"""
+import heapq
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse
+import scipy.sparse.csgraph
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from paper_1905_09317_amd import inputs
+
+DR = [0, -1, -1, -1, 0, 1, 1, 1]
+DC = [1, 1, 0, -1, -1, -1, 0, 1]
+
+
+def axis_dist(cs):
+    dd = math.isqrt(2 * cs * cs)
+    if dd * dd < 2 * cs * cs:
+        dd += 1
+    return [cs if k % 2 == 0 else dd for k in range(8)]
+
+
+def static_dijkstra(rows, cols, fuel, q8, D, src):
+    """Shortest paths with per-axis hop cost ceil(D_k/q_k) on burnable cells."""
+    n = rows * cols
+    ii, jj, ww = [], [], []
+    for r in range(rows):
+        for c in range(cols):
+            i = r * cols + c
+            if fuel[i] == 0:
+                continue
+            for k in range(8):
+                rr, cc = r + DR[k], c + DC[k]
+                if 0 <= rr < rows and 0 <= cc < cols and fuel[rr * cols + cc] != 0 and q8[i][k] > 0:
+                    ii.append(i)
+                    jj.append(rr * cols + cc)
+                    ww.append(-(-D[k] // q8[i][k]))
+    g = scipy.sparse.csr_matrix((ww, (ii, jj)), shape=(n, n))
+    return scipy.sparse.csgraph.dijkstra(g, directed=True, indices=src)
+
+
+def td_dijkstra(rows, cols, fuel, q_of, accept_of, ign, T, P, D):
+    """Label-setting Dijkstra with time-dependent axis travel.
+
+    q_of(cell, period) -> 8 integer axis rates; accept_of(cell, period) -> bool.
+    A fire leaving cell i at minute a advances q(i, p(m)) metres along an axis
+    in each minute m > a; the neighbour's centre is reached in the first
+    minute the total covers D; it ignites then, or at the start of the first
+    later period whose rate exceeds the threshold.
+    """
+    INF = 1 << 40
+    arr = np.full(rows * cols, INF, np.int64)
+    if ign < 0 or fuel[ign] == 0:
+        return arr
+    arr[ign] = 0
+    heap = [(0, ign)]
+    done = np.zeros(rows * cols, bool)
+    while heap:
+        a, i = heapq.heappop(heap)
+        if done[i] or a != arr[i]:
+            continue
+        done[i] = True
+        r, c = divmod(i, cols)
+        for k in range(8):
+            rr, cc = r + DR[k], c + DC[k]
+            if not (0 <= rr < rows and 0 <= cc < cols):
+                continue
+            j = rr * cols + cc
+            if fuel[j] == 0 or done[j]:
+                continue
+            rem, m0, t = D[k], a + 1, None
+            while m0 <= T:
+                p = (m0 - 1) // P
+                e = min((p + 1) * P, T)
+                q = int(q_of(i, p)[k])
+                if q > 0 and q * (e - m0 + 1) >= rem:
+                    t = m0 + (rem + q - 1) // q - 1
+                    break
+                rem -= q * (e - m0 + 1)
+                m0 = e + 1
+            if t is None:
+                continue
+            while t <= T and not accept_of(j, (t - 1) // P):
+                t = ((t - 1) // P + 1) * P + 1
+            if t <= T and t < arr[j]:
+                arr[j] = t
+                heapq.heappush(heap, (t, j))
+    return arr
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_tiny_c2_matches_static_dijkstra():
+    w = inputs.tiny_c2()
+    res = oracle.simulate(w.fuel, w.elev, w.weather, n_periods=w.n_periods,
+                          ignition_cell=w.ignition_cell)
+    q = oracle.eval_ros(w.fuel, w.elev, w.weather)["q8"]
+    assert q[0].tolist() == [18, 4, 1, 1, 1, 1, 1, 4]
+    dist = static_dijkstra(20, 20, w.fuel.ravel(), q, axis_dist(100), w.ignition_cell)
+    T = w.n_periods * 60
+    want = np.where(dist <= T, dist, -1).astype(np.int64)
+    assert np.array_equal(res["arrival_minute"][0], want)
+    assert res["burned_cells"][0] == 226 == int((dist <= T).sum())
+    am = res["arrival_minute"][0].reshape(20, 20)
+    # hop costs E 6, NE/SE 36, N/S/W 100, NW/SW 142; zig-zags beat straight runs
+    assert am[10, 11] == 6 and am[10, 19] == 54 and am[9, 11] == 36 and am[9, 12] == 42
+    assert am[9, 10] == 100 and am[11, 9] == 142 and am[8, 10] == 178 and am[4, 10] == 534
+    ap = res["arrival_period"][0].reshape(20, 20)
+    assert ap[10, 10] == 0 and ap[9, 10] == 1 and ap[8, 10] == 2 and ap[4, 10] == 8
+
+
+def test_zero_wind_octagon_closed_form():
+    """FFMC 90, BUI 80, no wind, C-2: every axis rate is 4.469 m/min -> 4, so
+    orthogonal hops cost 25 min and diagonal ones 36 (36 <= 2 x 25), and the
+    arrival at offset (dx, dy) is 25 (max - min) + 36 min."""
+    fuel = np.full((5, 5), 2, np.uint8)
+    wx = inputs.constant_weather(1, 90.0, 80.0, 0.0, 0.0)
+    q = oracle.eval_ros(fuel, None, wx)["q8"]
+    assert np.all(q[fuel.ravel() != 0] == 4)
+    res = oracle.simulate(fuel, None, wx, n_periods=1, ignition_cell=12)
+    am = res["arrival_minute"][0].reshape(5, 5)
+    for r in range(5):
+        for c in range(5):
+            dx, dy = abs(c - 2), abs(r - 2)
+            t = 25 * (max(dx, dy) - min(dx, dy)) + 36 * min(dx, dy)
+            assert am[r, c] == (t if t <= 60 else -1)
+    assert res["burned_cells"][0] == 13
+
+
+@pytest.mark.parametrize("ffmc,bui", [(90.0, 80.0), (86.0, 30.0), (94.0, 120.0)])
+def test_zero_wind_dihedral_symmetry(ffmc, bui):
+    n = 21
+    fuel = np.full((n, n), 3, np.uint8)
+    wx = inputs.constant_weather(6, ffmc, bui, 0.0, 0.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=6, ignition_cell=(n // 2) * n + n // 2)
+    am = res["arrival_minute"][0].reshape(n, n)
+    for g in (np.rot90(am), np.rot90(am, 2), np.rot90(am, 3), am.T, am[::-1], am[:, ::-1]):
+        assert np.array_equal(am, g)
+
+
+def test_wind_axis_extents_under_east_wind():
+    """With wind from the west on uniform fuel the scar runs east farthest:
+    east extent = floor(T / w_E) cells, west = floor(T / w_W)."""
+    w = inputs.tiny_c2(rows=41, cols=81, n_periods=4, ws=15.0)
+    q = oracle.eval_ros(w.fuel, None, w.weather)["q8"][0]
+    D = axis_dist(100)
+    cost = [-(-D[k] // q[k]) if q[k] > 0 else 10**9 for k in range(8)]
+    res = oracle.simulate(w.fuel, None, w.weather, n_periods=4, ignition_cell=20 * 81 + 40)
+    scar = res["scar"][0].reshape(41, 81)
+    row = np.nonzero(scar[20])[0]
+    T = 240
+    assert row.max() - 40 == min(40, T // cost[0])
+    assert 40 - row.min() == min(40, T // cost[4])
+
+
+def test_nonfuel_wall_blocks_spread():
+    fuel = np.full((15, 15), 2, np.uint8)
+    fuel[:, 7] = 0
+    wx = inputs.constant_weather(12, 94.0, 120.0, 40.0, 270.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=12, ignition_cell=7 * 15 + 3)
+    scar = res["scar"][0].reshape(15, 15)
+    assert scar[:, 7].sum() == 0 and scar[:, 8:].sum() == 0 and scar[:, :7].sum() > 20
+
+
+def test_nonburnable_ignition_burns_nothing():
+    fuel = np.full((6, 6), 2, np.uint8)
+    fuel[2, 2] = 0
+    wx = inputs.constant_weather(2, 90.0, 80.0, 20.0, 270.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=2, ignition_cell=14)
+    assert res["burned_cells"][0] == 0 and res["scar"].sum() == 0
+
+
+def test_all_nonfuel_uniform_ignition():
+    fuel = np.zeros((4, 4), np.uint8)
+    wx = inputs.constant_weather(2, 90.0, 80.0, 20.0, 270.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=2, reps=3, ignition_mode=1)
+    assert res["burned_cells"].tolist() == [0, 0, 0]
+    assert res["ignition_cell"].tolist() == [-1, -1, -1]
+
+
+def test_single_cell_grid():
+    fuel = np.full((1, 1), 5, np.uint8)
+    wx = inputs.constant_weather(1, 90.0, 80.0, 20.0, 270.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=1, ignition_mode=2)
+    assert res["scar"].tolist() == [[1]] and res["arrival_period"].tolist() == [[0]]
+
+
+def test_nearest_centre_ignition_ties_take_lowest_index():
+    fuel = np.full((6, 6), 2, np.uint8)
+    fuel[3, 3] = 0                       # centre (rows/2, cols/2) is not burnable
+    wx = inputs.constant_weather(1, 90.0, 80.0, 0.0, 0.0)
+    res = oracle.simulate(fuel, None, wx, n_periods=1, ignition_mode=2)
+    assert res["ignition_cell"][0] == 2 * 6 + 3   # (2,3), (3,2), (3,4), (4,3) tie at d^2 = 1
+
+
+# ----------------------------------------------- time-dependent Dijkstra pin
+
+def _random_case(seed, rows, cols, n_periods, P, sigma, rounding, threshold, slope):
+    rng = np.random.default_rng(seed)
+    fuel = rng.integers(0, 16, size=(rows, cols)).astype(np.uint8)
+    fuel[rng.random((rows, cols)) < 0.6] = rng.integers(1, 16)   # patches of one fuel
+    elev = rng.integers(0, 120, size=(rows, cols)).astype(np.int16) if slope else None
+    wx = np.zeros((2, n_periods, 4), np.float32)
+    wx[..., 0] = rng.uniform(80, 96, (2, n_periods))
+    wx[..., 1] = rng.uniform(0, 150, (2, n_periods))
+    wx[..., 2] = rng.uniform(0, 50, (2, n_periods))
+    wx[..., 3] = rng.uniform(0, 360, (2, n_periods))
+    return dict(fuel=fuel, elev=elev, weather=wx, n_periods=n_periods, period_min=P,
+                sigma=sigma, rounding=rounding, threshold=threshold)
+
+
+def _check_against_td_dijkstra(case, reps, seed):
+    fuel, elev, wx = case["fuel"], case["elev"], case["weather"]
+    rows, cols = fuel.shape
+    P, Np = case["period_min"], case["n_periods"]
+    kw = dict(n_periods=Np, period_min=P, reps=reps, seed=seed, sigma=case["sigma"],
+              threshold=case["threshold"], rounding=case["rounding"], ignition_mode=1,
+              scenario_mode=1)
+    res = oracle.simulate(fuel, elev, wx, **kw)
+    D = axis_dist(100)
+    for r in range(reps):
+        scen = int(res["scenario"][r])
+        ev = [oracle.eval_ros(fuel, elev, wx, scenario=scen, period=p, rep=r, seed=seed,
+                              sigma=case["sigma"], rounding=case["rounding"]) for p in range(Np)]
+        arr = td_dijkstra(rows, cols, fuel.ravel(), lambda i, p: ev[p]["q8"][i],
+                          lambda j, p: ev[p]["hros"][j] > case["threshold"],
+                          int(res["ignition_cell"][r]), Np * P, P, D)
+        want = np.where(arr < (1 << 40), arr, -1)
+        assert np.array_equal(res["arrival_minute"][r], want), (r, scen)
+        assert res["burned_cells"][r] == (want >= 0).sum()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_td_dijkstra_random_grids(seed):
+    case = _random_case(seed, 11, 13, n_periods=10, P=[7, 13, 30, 60, 5, 9][seed],
+                        sigma=[0.0, 0.15, 0.3, 0.15, 0.0, 0.5][seed], rounding=seed % 2,
+                        threshold=0.0, slope=seed % 3 != 0)
+    _check_against_td_dijkstra(case, reps=3, seed=100 + seed)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_td_dijkstra_with_ignition_threshold(seed):
+    """A reached cell whose own rate is below the threshold waits for the
+    first later period whose rate passes it (messages persist)."""
+    thr = [3.0, 6.0, 2.0, 10.0][seed]
+    case = _random_case(50 + seed, 16, 16, n_periods=8, P=20, sigma=0.3, rounding=1,
+                        threshold=thr, slope=True)
+    case["weather"][..., 0] = np.clip(case["weather"][..., 0] + 4, 0, 101)
+    _check_against_td_dijkstra(case, reps=3, seed=7 + seed)
+    # the threshold must actually delay some ignitions in this case
+    kw = dict(n_periods=8, period_min=20, reps=3, seed=7 + seed, sigma=0.3, rounding=1,
+              ignition_mode=1, scenario_mode=1)
+    a = oracle.simulate(case["fuel"], case["elev"], case["weather"], threshold=thr, **kw)
+    b = oracle.simulate(case["fuel"], case["elev"], case["weather"], threshold=0.0, **kw)
+    assert (a["arrival_minute"] != b["arrival_minute"]).sum() > 0
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(seed=st.integers(0, 10**6), rows=st.integers(1, 9), cols=st.integers(1, 9),
+       P=st.integers(1, 60), n_periods=st.integers(1, 8), sigma=st.sampled_from([0.0, 0.2]),
+       rounding=st.integers(0, 1), threshold=st.sampled_from([0.0, 0.0, 3.0]))
+def test_td_dijkstra_property(seed, rows, cols, P, n_periods, sigma, rounding, threshold):
+    case = _random_case(seed, rows, cols, n_periods, P, sigma, rounding, threshold, slope=True)
+    _check_against_td_dijkstra(case, reps=2, seed=seed)
+
+
+def test_override_replays_given_rates():
+    """Overriding the ignition cell's rates for period 0 with zeros holds the
+    fire there until period 1."""
+    w = inputs.tiny_c2(n_periods=3)
+    ign = w.ignition_cell
+    keys = np.array([[0, 0, ign]], np.int32)
+    q = np.zeros((1, 8), np.int32)
+    res = oracle.simulate(w.fuel, None, w.weather, n_periods=3, ignition_cell=ign,
+                          overrides=(keys, q))
+    base = oracle.simulate(w.fuel, None, w.weather, n_periods=3, ignition_cell=ign)
+    am, bm = res["arrival_minute"][0], base["arrival_minute"][0]
+    assert am[ign + 1] == 60 + 6 and bm[ign + 1] == 6
+
+
+# ------------------------------------------------------------- invariants
+
+def test_rep_split_additivity_and_totals():
+    w = inputs.batched_monte_carlo(side=24, reps=8, n_scenarios=3, n_periods=4)
+    kw = dict(cell_m=100, n_periods=4, seed=w.seed, sigma=w.sigma, rounding=w.rounding,
+              ignition_mode=1, scenario_mode=1)
+    full = oracle.simulate(w.fuel, w.elev, w.weather, reps=8, **kw)
+    a = oracle.simulate(w.fuel, w.elev, w.weather, reps=3, rep_offset=0, **kw)
+    b = oracle.simulate(w.fuel, w.elev, w.weather, reps=5, rep_offset=3, **kw)
+    assert np.array_equal(full["burn_count"], a["burn_count"] + b["burn_count"])
+    assert np.array_equal(full["scar"], np.concatenate([a["scar"], b["scar"]]))
+    assert np.array_equal(full["burned_cells"], full["scar"].sum(axis=1))
+    assert np.array_equal(full["burn_count"], full["scar"].sum(axis=0))
+    assert np.array_equal(full["scar"], (full["arrival_minute"] >= 0).astype(np.uint8))
+
+
+def test_area_monotone_in_duration_ffmc_and_bui():
+    fuel = inputs.fuel_grid(48, 48, 3)
+    fuel[24, 24] = 2
+
+    def area(n_periods=6, ffmc=90.0, bui=80.0):
+        wx = inputs.constant_weather(8, ffmc, bui, 15.0, 250.0)
+        return oracle.simulate(fuel, None, wx, n_periods=n_periods,
+                               ignition_cell=24 * 48 + 24)["burned_cells"][0]
+
+    a = [area(n_periods=k) for k in range(1, 9)]
+    assert all(x <= y for x, y in zip(a, a[1:]))
+    b = [area(ffmc=f) for f in (84.0, 87.0, 90.0, 93.0, 96.0)]
+    assert all(x <= y for x, y in zip(b, b[1:]))
+    c = [area(bui=v) for v in (20.0, 50.0, 80.0, 120.0)]
+    assert all(x <= y for x, y in zip(c, c[1:]))
+
+
+def test_arrival_monotone_in_noise_free_multiplier():
+    """Raising every axis rate never delays any arrival (the fixed point is
+    monotone in q): with the same rounding uniforms, a higher FFMC on flat
+    uniform fuel gives arrivals no later anywhere."""
+    fuel = np.full((25, 25), 4, np.uint8)
+    lo = oracle.simulate(fuel, None, inputs.constant_weather(4, 88.0, 70.0, 12.0, 200.0),
+                         n_periods=4, ignition_cell=312, rounding=1, seed=5)
+    hi = oracle.simulate(fuel, None, inputs.constant_weather(4, 92.0, 70.0, 12.0, 200.0),
+                         n_periods=4, ignition_cell=312, rounding=1, seed=5)
+    a, b = lo["arrival_minute"][0], hi["arrival_minute"][0]
+    assert np.all((b >= 0)[a >= 0])
+    assert np.all(b[a >= 0] <= a[a >= 0])
+
+
+def test_invalid_inputs_rejected():
+    fuel = np.full((3, 3), 2, np.uint8)
+    wx = inputs.constant_weather(2, 90.0, 80.0, 20.0, 270.0)
+    with pytest.raises(ValueError):
+        oracle.simulate(fuel, None, wx, n_periods=3)          # more periods than weather
+    bad = fuel.copy()
+    bad[0, 0] = 16
+    with pytest.raises(ValueError):
+        oracle.simulate(bad, None, wx, n_periods=1)
+    with pytest.raises(ValueError):
+        oracle.simulate(fuel, None, wx, n_periods=1, ignition_cell=9)
