@@ -1,0 +1,213 @@
+/*
+ * c2f.h -- C ABI of libc2f.so, an MI355X (gfx950) implementation of the
+ * Cell2Fire fire-growth hot path (Pais, Carrasco, Martell, Weintraub,
+ * Woodruff, "Cell2Fire: A Cell Based Forest Fire Growth Model").
+ *
+ * What the library computes
+ *   A landscape is a rectangular grid of square cells, each with a fuel type
+ *   and an elevation (Section 3.1; inputs of Section 3.5).  For every burning
+ *   cell and weather period it evaluates the FBP System head, back and flank
+ *   rates and length-to-breadth ratio (Sections 2.3 and 3.7, assumption A2),
+ *   fits the ellipse of eqs. (2)-(4), and spreads fire along the 8
+ *   centre-to-centre axes at the rate of eq. (1).  A neighbour whose centre
+ *   is reached receives a message and ignites if its own rate passes the
+ *   threshold (Section 3.1; Algorithm 1 Step 2).  The clock advances in
+ *   whole minutes; weather changes every period.  Many stochastic
+ *   replications (ROS noise, weather scenario, ignition cell; Section 3.1,
+ *   sources of uncertainty (1)-(3)) are run and folded into burn-count maps
+ *   (Section 3.6 (i)).
+ *
+ * Conventions shared by all entry points
+ *   - Grids are row-major, row 0 is the northern edge, cell index
+ *     i = row * cols + col.  Axis order everywhere: E, NE, N, NW, W, SW, S,
+ *     SE (0 deg = East, counter-clockwise, Section 3.4 step i).
+ *   - Fuel codes: 0 non-fuel, 1-7 C-1..C-7, 8 D-1, 9 M-1, 10 M-2,
+ *     11-13 S-1..S-3, 14 O-1a, 15 O-1b (Table FBPT gives the dictionary idea).
+ *   - Every function returns a c2f_status; nothing is thrown or aborted
+ *     across the ABI.  On failure, outputs are not written and
+ *     c2f_last_error() describes the cause.
+ *   - Host pointers passed in are only read during the call; the library
+ *     copies what it keeps.  All device memory is owned by the context and
+ *     released by c2f_destroy().
+ *   - One context per host thread for c2f_simulate/c2f_eval_ros; the
+ *     serving calls (c2f_submit/poll/wait) may be used from several threads.
+ *   - Results depend only on (landscape, weather, params including seed):
+ *     never on block size, batch composition or co-resident work.
+ */
+#ifndef C2F_H
+#define C2F_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    C2F_OK = 0,
+    C2F_EINVAL = -1,    /* bad argument, shape or value */
+    C2F_ENOMEM = -2,    /* device allocation failed or HBM budget exceeded */
+    C2F_EDEVICE = -3,   /* HIP runtime error or no suitable device */
+    C2F_ECAPACITY = -4, /* work lists overflowed even at the largest capacity */
+    C2F_ESTATE = -5,    /* unknown landscape/weather id or ticket, or wrong call order */
+    C2F_EBUSY = -6      /* serving queue is full */
+} c2f_status;
+
+typedef struct c2f_ctx c2f_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * device memory the context may hold (0 = no cap beyond the device).
+ * Loads the code object and allocates nothing else yet. */
+c2f_status c2f_create(int32_t device, uint64_t hbm_budget_bytes, c2f_ctx** out);
+
+/* Release every device allocation and the context.  NULL is allowed. */
+void c2f_destroy(c2f_ctx* ctx);
+
+/* Text of the last error on this context (empty if none).  Valid until the
+ * next call on the context. */
+const char* c2f_last_error(const c2f_ctx* ctx);
+
+/* Order all later work on `hip_stream` (a hipStream_t, e.g. torch's current
+ * stream); NULL selects the context's own stream.  Default priority only. */
+c2f_status c2f_set_stream(c2f_ctx* ctx, void* hip_stream);
+
+/* Upload a landscape (Section 3.5 (i)): fuel codes [rows*cols] (host) and
+ * elevations in metres [rows*cols] (host; NULL = flat ground).  cell_m is
+ * the cell width in metres (1..20000).  pc_pct is the percent conifer of
+ * M-1/M-2 stands (0..100), curing_pct the grass curing of O-1 (0 < c <= 100).
+ * Slope (percent) and upslope azimuth are derived on the device from Horn's
+ * 3x3 gradient with replicated edges; EINVAL if a gradient numerator
+ * exceeds the int16 range (a rise of more than ~4 km across one cell).
+ * Writes a new id to *landscape_id. */
+c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t cell_m,
+                              const uint8_t* fuel, const int16_t* elev_m, float pc_pct,
+                              float curing_pct, int32_t* landscape_id);
+c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id);
+
+/* One weather record (Table WeatherT columns used by the FBP System):
+ * FFMC (0..101), BUI (>= 0), wind speed km/h (>= 0) and the azimuth the
+ * wind blows FROM, degrees clockwise from north. */
+typedef struct {
+    float ffmc, bui, ws_kmh, wd_deg_from;
+} c2f_weather_row;
+
+/* Upload weather scenarios (Section 3.5 (iv)): rows [n_scen][n_periods]
+ * (host), one record per period of period_min minutes.  Writes an id. */
+c2f_status c2f_set_weather(c2f_ctx* ctx, int32_t n_scen, int32_t n_periods, int32_t period_min,
+                           const c2f_weather_row* rows, int32_t* weather_id);
+c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
+
+/* Parameters of one Monte-Carlo simulation request.
+ *   reps           replications (>= 1); rep index r uses the global index
+ *                  rep_offset + r in every random draw, so a run split into
+ *                  rep ranges reproduces the unsplit run exactly.
+ *   n_periods      fire periods to simulate (<= the weather's periods);
+ *                  the fire runs for n_periods * period_min minutes.
+ *   seed           Philox4x32-10 key (low word, high word).
+ *   ros_sigma      lognormal ROS noise: every rate of a cell in a period is
+ *                  multiplied by exp(sigma Z - sigma^2/2) (0 = off).
+ *   ros_threshold  a reached cell ignites only if its head rate exceeds this
+ *                  (m/min; Section 3.1); otherwise it stays reached and
+ *                  ignites at the start of the first later period that passes.
+ *   rounding       axis rates are integer m/min: 0 = floor(x + 1/2),
+ *                  1 = floor(x + u) with u uniform from Philox.
+ *   precision      0 = FBP evaluated in FP64, 1 = in FP32.
+ *   ignition_mode  0 = ignition_cell, 1 = uniform over burnable cells,
+ *                  2 = the burnable cell nearest (rows/2, cols/2).
+ *   scenario_mode  0 = scenario, 1 = uniform over the weather's scenarios. */
+typedef struct {
+    int32_t landscape_id, weather_id, reps, n_periods;
+    uint64_t seed;
+    float ros_sigma, ros_threshold;
+    int32_t rounding, precision;
+    int32_t ignition_mode, ignition_cell;
+    int32_t scenario_mode, scenario;
+    int32_t rep_offset;
+} c2f_sim_params;
+
+/* Outputs of a simulation (Section 3.6 (i) burn grids and their counts).
+ * Any pointer may be NULL (not wanted).  With on_device = 0 they are host
+ * pointers; with 1 they are device pointers (e.g. torch tensors'
+ * data_ptr()) written in order on the context's stream.
+ *   scar           uint8  [reps][rows*cols]  1 = ignited within the run
+ *   arrival_period int32  [reps][rows*cols]  -1 unburned, 0 ignition cell,
+ *                                            else (minute - 1) / period_min
+ *   arrival_minute int32  [reps][rows*cols]  -1 unburned, else minute
+ *   burn_count     uint32 [rows*cols]        number of reps that burned it
+ *   burned_cells   int64  [reps]             cells burned per rep
+ *   ignition_cell  int32  [reps]             -1 if no burnable cell
+ *   scenario       int32  [reps]                                           */
+typedef struct {
+    uint8_t* scar;
+    int32_t* arrival_period;
+    int32_t* arrival_minute;
+    uint32_t* burn_count;
+    int64_t* burned_cells;
+    int32_t* ignition_cell;
+    int32_t* scenario;
+    int32_t on_device;
+} c2f_outputs;
+
+/* Run one simulation request to completion (synchronous). */
+c2f_status c2f_simulate(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out);
+
+/* Run several requests, possibly on different landscapes and weather, in
+ * one fused launch (synchronous).  params[n_jobs], out[n_jobs]. */
+c2f_status c2f_simulate_batch(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* params,
+                              const c2f_outputs* out);
+
+/* Parity/debug: the per-cell FBP field of one (scenario, period, rep) on the
+ * landscape, exactly as the simulation computes it.  Host outputs, any may
+ * be NULL, each [rows*cols] (q8 and x8: [rows*cols][8]):
+ * hros/bros/fros m/min including the rep's noise multiplier, lb, raz_deg
+ * (spread azimuth, clockwise from north), x8 the unquantised axis rates
+ * (eq. (1) times the multiplier), q8 the integer axis rates.  Non-fuel
+ * cells give zeros. */
+c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, int32_t scenario,
+                        int32_t period, int32_t rep, uint64_t seed, float sigma, int32_t rounding,
+                        int32_t precision, double* hros, double* bros, double* fros, double* lb,
+                        double* raz_deg, double* x8, int32_t* q8);
+
+/* FBP coefficients (a, b, c, q, BUI0) of fuel code 1..15 as the device uses
+ * them (M-1/M-2 report zeros for a, b, c).  Host-only, needs no device. */
+c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]);
+
+/* Tuning.  block_threads: threads per work group of the propagation kernel
+ * (64..1024, multiple of 64; 0 = automatic).  list_capacity: entries per
+ * per-replication work list (0 = automatic).  A too small capacity is
+ * detected and the run repeated with a larger one, so results never change. */
+c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capacity);
+
+/* Pick block size and list capacity for requests like `representative` by
+ * timing candidates on the device; the choice is kept for requests of the
+ * same grid size and replication count. */
+c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* representative);
+
+/* Counters of the most recent simulate/simulate_batch call. */
+typedef struct {
+    int64_t ignitions;       /* cells ignited, summed over reps */
+    int64_t entries;         /* work-list entries processed (incl. stale) */
+    int64_t rate_evals;      /* per (cell, period) rate evaluations */
+    int64_t candidates;      /* arrival candidates offered to neighbours */
+    int64_t improvements;    /* candidates that lowered an arrival */
+    int64_t relaunches;      /* repeats after a work-list overflow */
+    double kernel_ms;        /* propagation kernel time (HIP events) */
+    int32_t block_threads, grid_blocks;
+    int64_t list_capacity;
+} c2f_run_stats;
+c2f_status c2f_get_stats(const c2f_ctx* ctx, c2f_run_stats* out);
+
+/* Serving: submit a request; it is admitted to the device when its memory
+ * fits the context's budget, batched with other admitted requests, and
+ * completed asynchronously.  Output pointers must stay valid until done.
+ * EBUSY when max_queue requests are already waiting. */
+c2f_status c2f_submit(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out,
+                      uint64_t* ticket);
+c2f_status c2f_poll(c2f_ctx* ctx, uint64_t ticket, int32_t* done);
+c2f_status c2f_wait(c2f_ctx* ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* C2F_H */

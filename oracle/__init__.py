@@ -39,6 +39,8 @@ def _load():
         L.oracle_philox4x32_10.argtypes = [P, P, P]
         L.oracle_philox4x32_10.restype = None
         L.oracle_horn.argtypes = [i32, i32, P, P, P]
+        L.oracle_fuel_coefficients.argtypes = [i32, P]
+        L.oracle_fuel_coefficients.restype = ctypes.c_int
         L.oracle_fbp_point.argtypes = [i32, f64, f64, f64, f64, f64, f64, f64, f64, P]
         L.oracle_axis_ros.argtypes = [f64, f64, f64, f64, P]
         L.oracle_axis_ros.restype = None
@@ -62,6 +64,13 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
     _load().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def fuel_coefficients(fuel: int) -> np.ndarray:
+    out = np.zeros(5, np.float64)
+    if _load().oracle_fuel_coefficients(int(fuel), _ptr(out)) != 0:
+        raise ValueError("bad fuel code")
     return out
 
 

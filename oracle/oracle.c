@@ -69,6 +69,13 @@ static const double FBP_Q[16] = {0, 0.90, 0.70, 0.75, 0.80, 0.80, 0.80, 0.85, 0.
                                  0.75, 0.75, 0.75, 1.0, 1.0};
 static const double FBP_BUI0[16] = {0, 72, 64, 62, 66, 56, 62, 106, 32, 50, 50, 38, 63, 31, 1, 1};
 
+int oracle_fuel_coefficients(int32_t fuel, double* out5) {
+    if (fuel < 1 || fuel > 15 || !out5) return -1;
+    out5[0] = FBP_A[fuel]; out5[1] = FBP_B[fuel]; out5[2] = FBP_C[fuel];
+    out5[3] = FBP_Q[fuel]; out5[4] = FBP_BUI0[fuel];
+    return 0;
+}
+
 /* ------------------------------------------------------ FBP System model */
 
 /* Fine fuel moisture content from FFMC, and the fine-fuel function f(F). */

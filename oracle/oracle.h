@@ -23,6 +23,9 @@ extern "C" {
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* The oracle's FBP coefficients (a, b, c, q, BUI0) of fuel code 1..15. */
+int oracle_fuel_coefficients(int32_t fuel, double* out5);
+
 /* Horn 3x3 gradient numerators with edge replication (east, north). */
 int oracle_horn(int32_t rows, int32_t cols, const int16_t* elev, int32_t* gx, int32_t* gn);
 

@@ -1,0 +1,259 @@
+"""Python front end of libc2f: argument marshalling only.
+
+Every step of the simulation runs in the HIP library; this module converts
+numpy arrays and torch tensors to the C ABI of include/c2f.h and back.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib
+from ._lib import Outputs, RunStats, SimParams, WeatherRow
+
+OUTPUT_NAMES = ("scar", "arrival_period", "arrival_minute", "burn_count", "burned_cells",
+                "ignition_cell", "scenario")
+_PER_REP_CELLS = {"scar": np.uint8, "arrival_period": np.int32, "arrival_minute": np.int32}
+_PER_REP = {"burned_cells": np.int64, "ignition_cell": np.int32, "scenario": np.int32}
+
+
+class C2FError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_lib.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+@dataclass
+class Request:
+    """One Monte-Carlo simulation request (mirrors c2f_sim_params)."""
+    landscape: int
+    weather: int
+    n_periods: int
+    reps: int = 1
+    seed: int = 0
+    sigma: float = 0.0
+    threshold: float = 0.0
+    rounding: int = 0
+    precision: int = 0
+    ignition_mode: int = 0
+    ignition_cell: int = 0
+    scenario_mode: int = 0
+    scenario: int = 0
+    rep_offset: int = 0
+    outputs: tuple = OUTPUT_NAMES
+    device_out: bool = False
+
+    def params(self) -> SimParams:
+        return SimParams(self.landscape, self.weather, self.reps, self.n_periods,
+                         int(self.seed) & (2**64 - 1), float(self.sigma), float(self.threshold),
+                         self.rounding, self.precision, self.ignition_mode, self.ignition_cell,
+                         self.scenario_mode, self.scenario, self.rep_offset)
+
+
+@dataclass
+class _Landscape:
+    rows: int
+    cols: int
+    cell_m: int
+
+
+class Simulator:
+    """A device context holding landscapes and weather streams in HBM."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._L = _lib.load()
+        self._ctx = ctypes.c_void_p()
+        st = self._L.c2f_create(int(device), int(hbm_budget_bytes), ctypes.byref(self._ctx))
+        if st != 0:
+            raise C2FError(st, f"c2f_create(device={device}) failed (a gfx950 GPU is required)")
+        self._lands: dict[int, _Landscape] = {}
+        self._device = device
+        self._keep = {}
+
+    # ----------------------------------------------------------- plumbing
+    def _check(self, st: int):
+        if st != 0:
+            msg = self._L.c2f_last_error(self._ctx)
+            raise C2FError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if self._ctx:
+            self._L.c2f_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        """Order library work on a HIP stream (a torch.cuda.Stream, an int handle, or None)."""
+        handle = None
+        if stream is not None:
+            handle = getattr(stream, "cuda_stream", stream)
+        self._check(self._L.c2f_set_stream(self._ctx, ctypes.c_void_p(handle)))
+
+    # ------------------------------------------------------------- inputs
+    def load_landscape(self, fuel, elev=None, cell_m: int = 100, pc: float = 50.0,
+                       curing: float = 80.0) -> int:
+        f = np.ascontiguousarray(fuel, dtype=np.uint8)
+        if f.ndim != 2:
+            raise ValueError("fuel must be a 2-D grid")
+        e = None
+        if elev is not None:
+            e = np.ascontiguousarray(elev, dtype=np.int16)
+            if e.shape != f.shape:
+                raise ValueError("elevation shape differs from fuel shape")
+        lid = ctypes.c_int32()
+        self._check(self._L.c2f_load_landscape(
+            self._ctx, f.shape[0], f.shape[1], int(cell_m), f.ctypes.data_as(ctypes.c_void_p),
+            None if e is None else e.ctypes.data_as(ctypes.c_void_p), float(pc), float(curing),
+            ctypes.byref(lid)))
+        self._lands[lid.value] = _Landscape(f.shape[0], f.shape[1], int(cell_m))
+        return lid.value
+
+    def unload_landscape(self, landscape: int):
+        self._check(self._L.c2f_unload_landscape(self._ctx, int(landscape)))
+        self._lands.pop(landscape, None)
+
+    def set_weather(self, weather, period_min: int = 60) -> int:
+        w = np.ascontiguousarray(weather, dtype=np.float32)
+        if w.ndim == 2:
+            w = w[None]
+        if w.ndim != 3 or w.shape[2] != 4:
+            raise ValueError("weather must be [scenarios, periods, 4]")
+        wid = ctypes.c_int32()
+        self._check(self._L.c2f_set_weather(self._ctx, w.shape[0], w.shape[1], int(period_min),
+                                            w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(wid)))
+        return wid.value
+
+    def unset_weather(self, weather: int):
+        self._check(self._L.c2f_unset_weather(self._ctx, int(weather)))
+
+    # ------------------------------------------------------------ outputs
+    def _alloc_outputs(self, req: Request):
+        lm = self._lands[req.landscape]
+        n = lm.rows * lm.cols
+        shapes = {"scar": (req.reps, n), "arrival_period": (req.reps, n),
+                  "arrival_minute": (req.reps, n), "burn_count": (n,), "burned_cells": (req.reps,),
+                  "ignition_cell": (req.reps,), "scenario": (req.reps,)}
+        dtypes = {**_PER_REP_CELLS, **_PER_REP, "burn_count": np.uint32}
+        res = {}
+        o = Outputs()
+        o.on_device = 1 if req.device_out else 0
+        for name in req.outputs:
+            if req.device_out:
+                import torch
+                tdt = {np.uint8: torch.uint8, np.int32: torch.int32, np.int64: torch.int64,
+                       np.uint32: torch.int32}[dtypes[name]]
+                t = torch.empty(shapes[name], dtype=tdt, device=f"cuda:{self._device}")
+                res[name] = t
+                setattr(o, name, t.data_ptr())
+            else:
+                a = np.empty(shapes[name], dtype=dtypes[name])
+                res[name] = a
+                setattr(o, name, a.ctypes.data)
+        return res, o
+
+    def simulate(self, req: Request | None = None, **kw) -> dict:
+        """Run one request; returns the wanted outputs (numpy, or torch tensors
+        on the device with device_out=True; burn_count then has dtype int32
+        holding the uint32 bits)."""
+        req = req or Request(**kw)
+        if req.device_out:
+            import torch
+            self.set_stream(torch.cuda.current_stream(self._device))
+        res, o = self._alloc_outputs(req)
+        p = req.params()
+        self._check(self._L.c2f_simulate(self._ctx, ctypes.byref(p), ctypes.byref(o)))
+        return res
+
+    def simulate_batch(self, reqs: list[Request]) -> list[dict]:
+        """Run several requests (any landscapes/weather) in one fused launch."""
+        if any(r.device_out for r in reqs):
+            import torch
+            self.set_stream(torch.cuda.current_stream(self._device))
+        allocs = [self._alloc_outputs(r) for r in reqs]
+        P = (SimParams * len(reqs))(*[r.params() for r in reqs])
+        O = (Outputs * len(reqs))(*[a[1] for a in allocs])
+        self._check(self._L.c2f_simulate_batch(self._ctx, len(reqs), P, O))
+        return [a[0] for a in allocs]
+
+    def eval_ros(self, landscape: int, weather: int, *, scenario=0, period=0, rep=0, seed=0,
+                 sigma=0.0, rounding=0, precision=0) -> dict:
+        lm = self._lands[landscape]
+        n = lm.rows * lm.cols
+        out = {k: np.empty(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz")}
+        out["x8"] = np.empty((n, 8), np.float64)
+        out["q8"] = np.empty((n, 8), np.int32)
+        ptr = {k: v.ctypes.data_as(ctypes.c_void_p) for k, v in out.items()}
+        self._check(self._L.c2f_eval_ros(
+            self._ctx, int(landscape), int(weather), int(scenario), int(period), int(rep),
+            int(seed) & (2**64 - 1), float(sigma), int(rounding), int(precision), ptr["hros"],
+            ptr["bros"], ptr["fros"], ptr["lb"], ptr["raz"], ptr["x8"], ptr["q8"]))
+        return out
+
+    # ------------------------------------------------------------- tuning
+    def set_tuning(self, block_threads: int = 0, list_capacity: int = 0):
+        self._check(self._L.c2f_set_tuning(self._ctx, int(block_threads), int(list_capacity)))
+
+    def autotune(self, req: Request | None = None, **kw):
+        req = req or Request(**kw)
+        p = req.params()
+        self._check(self._L.c2f_autotune(self._ctx, ctypes.byref(p)))
+
+    def stats(self) -> dict:
+        s = RunStats()
+        self._check(self._L.c2f_get_stats(self._ctx, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in RunStats._fields_}
+
+    # ------------------------------------------------------------ serving
+    def submit(self, req: Request) -> tuple[int, dict]:
+        """Queue a request; returns (ticket, outputs that fill in when done)."""
+        res, o = self._alloc_outputs(req)
+        p = req.params()
+        t = ctypes.c_uint64()
+        self._check(self._L.c2f_submit(self._ctx, ctypes.byref(p), ctypes.byref(o), ctypes.byref(t)))
+        self._keep[t.value] = res
+        return t.value, res
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        self._check(self._L.c2f_poll(self._ctx, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> dict:
+        try:
+            self._check(self._L.c2f_wait(self._ctx, ctypes.c_uint64(ticket)))
+        finally:
+            res = self._keep.pop(ticket, None)
+        return res
+
+
+def fbp_coefficients(fuel: int) -> np.ndarray:
+    out = np.zeros(5, np.float64)
+    st = _lib.load().c2f_fbp_coefficients(int(fuel), out.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise C2FError(st, f"bad fuel code {fuel}")
+    return out
+
+
+def request_for(sim: Simulator, workload, landscape: int, weather: int, **over) -> Request:
+    """A Request reproducing a synthetic workload's settings."""
+    kw = dict(landscape=landscape, weather=weather, n_periods=workload.n_periods,
+              reps=workload.reps, seed=workload.seed, sigma=workload.sigma,
+              threshold=workload.threshold, rounding=workload.rounding,
+              precision=workload.precision, ignition_mode=workload.ignition_mode,
+              ignition_cell=workload.ignition_cell, scenario_mode=workload.scenario_mode,
+              scenario=workload.scenario)
+    kw.update(over)
+    return Request(**kw)

@@ -1,0 +1,248 @@
+// Device building blocks: Philox4x32-10, per-period weather terms, the FBP
+// rate evaluation of one cell, and the directional rates of eq. (1).
+// Everything is templated on the arithmetic type R (double or float).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fuel_table.h"
+#include "types.h"
+
+namespace c2f {
+
+// ------------------------------------------------------------------ math
+// Explicit precision dispatch so float code never widens to double.
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float m_pow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sin(double x) { return sin(x); }
+__device__ __forceinline__ float m_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double m_cos(double x) { return cos(x); }
+__device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double m_atan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float m_atan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double m_fmod(double x, double y) { return fmod(x, y); }
+__device__ __forceinline__ float m_fmod(float x, float y) { return fmodf(x, y); }
+
+template <typename R> struct Const;
+template <> struct Const<double> { static constexpr double pi = 3.14159265358979323846; };
+template <> struct Const<float> { static constexpr float pi = 3.14159265358979323846f; };
+
+// --------------------------------------------------------------- Philox
+// Philox4x32-10 block function (Salmon et al., SC'11): ten rounds of two
+// 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * x.x, hi0 = __umulhi(0xD2511F53u, x.x);
+        const uint32_t lo1 = 0xCD9E8D57u * x.z, hi1 = __umulhi(0xCD9E8D57u, x.z);
+        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return x;
+}
+
+// Counter layout shared by every random draw: (cell, period, rep, tag).
+// Tags: 0 ROS noise, 1-2 rounding uniforms for axes 0-3 / 4-7,
+// 3 ignition cell, 4 weather scenario (per-rep draws use cell = period = ~0).
+__device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t cell, uint32_t period, uint32_t rep,
+                                      uint32_t tag) {
+    return philox4x32_10(make_uint4(cell, period, rep, tag), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// 24-bit uniform in [0, 1) from the high bits of a 32-bit word (exact in float).
+template <typename R>
+__device__ __forceinline__ R unit24(uint32_t x) {
+    return (R)(x >> 8) * (R)(1.0 / 16777216.0);
+}
+
+// ------------------------------------------------------- weather terms
+// Per (scenario, period) quantities that do not depend on the cell; kept in
+// a table computed once per weather upload.  Layout of one row:
+//   [0] f(F)   [1] ISZ = 0.208 f(F)   [2] WS sin(WAZ)   [3] WS cos(WAZ)
+//   [4 + f] BUI effect of fuel f      [20 + f] zero-wind rate RSZ of pure fuel f
+
+template <typename R>
+struct CoefR {
+    R a, b, c, q, bui0;
+};
+
+// Rate of spread of one unmixed fuel: a (1 - exp(-b ISI))^c.
+template <typename R>
+__device__ __forceinline__ R rsi_pure(const CoefR<R>& k, R isi) {
+    return k.a * m_pow(-m_expm1(-k.b * isi), k.c);
+}
+
+// Fill one table row from FFMC, BUI, wind speed (km/h) and the azimuth the
+// wind comes from.  The fire heads downwind: WAZ = WD + 180 degrees.
+template <typename R>
+__device__ void weather_row(const CoefR<R>* coef, float ffmc_f, float bui_f, float ws_f, float wd_f,
+                            R* row) {
+    const R ffmc = (R)ffmc_f, bui = (R)bui_f, ws = (R)ws_f, wd = (R)wd_f;
+    const R m = (R)147.2 * ((R)101 - ffmc) / ((R)59.5 + ffmc);   // fine fuel moisture
+    const R ff = (R)91.9 * m_exp((R)-0.1386 * m) * ((R)1 + m_pow(m, (R)5.31) / (R)4.93e7);
+    const R isz = (R)0.208 * ff;
+    const R waz = m_fmod(wd + (R)180, (R)360) * (Const<R>::pi / (R)180);
+    row[0] = ff;
+    row[1] = isz;
+    row[2] = ws * m_sin(waz);
+    row[3] = ws * m_cos(waz);
+    for (int f = 0; f < kNumFuels; ++f) {
+        const CoefR<R>& k = coef[f];
+        R be = (R)1;
+        if (f != kNonFuel && bui > (R)0)
+            be = m_exp((R)50 * m_log(k.q) * ((R)1 / bui - (R)1 / k.bui0));
+        row[kRowBE + f] = be;
+        row[kRowRSZ + f] = (k.a > (R)0) ? rsi_pure(k, isz) : (R)0;
+    }
+}
+
+// ----------------------------------------------------------- cell rates
+// Landscape-wide constants of the mixed and grass fuels.
+template <typename R>
+struct LandR {
+    R pc_w;    // percent conifer / 100 (M-1, M-2)
+    R cf;      // grass curing factor (O-1a, O-1b)
+    R cell_m;  // cell width, metres
+};
+
+template <typename R>
+__device__ __forceinline__ R rsi_fuel(const CoefR<R>* coef, int f, R isi, const LandR<R>& L) {
+    if (f == kM1 || f == kM2) {
+        const R c2 = rsi_pure(coef[kC2], isi);
+        const R d1 = rsi_pure(coef[kD1], isi);
+        const R wd1 = (f == kM2) ? (R)0.2 * ((R)1 - L.pc_w) : ((R)1 - L.pc_w);
+        return L.pc_w * c2 + wd1 * d1;
+    }
+    const R r = rsi_pure(coef[f], isi);
+    return (f >= kO1a) ? r * L.cf : r;
+}
+
+// Spread index that gives rate rsf on the curve of fuel k (scaled by cfac),
+// with the curve's 0.01 floor inside the logarithm.
+template <typename R>
+__device__ __forceinline__ R isf_pure(const CoefR<R>& k, R rsf, R cfac) {
+    R t = (R)1 - m_pow(rsf / (cfac * k.a), (R)1 / k.c);
+    if (t < (R)0.01) t = (R)0.01;
+    return m_log(t) / -k.b;
+}
+
+// Slope-equivalent wind speed (km/h) for slope factor sf.
+__device__ __noinline__ double slope_wind(const CoefR<double>* coef, int f, double sf, const double* row,
+                                          const LandR<double>& L) {
+    const double ff = row[0], isz = row[1];
+    double isf;
+    if (f == kM1 || f == kM2) {
+        isf = L.pc_w * isf_pure(coef[kC2], sf * row[kRowRSZ + kC2], 1.0) +
+              (1.0 - L.pc_w) * isf_pure(coef[kD1], sf * row[kRowRSZ + kD1], 1.0);
+    } else if (f >= kO1a) {
+        isf = isf_pure(coef[f], sf * row[kRowRSZ + f] * L.cf, L.cf);
+    } else {
+        isf = isf_pure(coef[f], sf * row[kRowRSZ + f], 1.0);
+    }
+    double wse = log(isf / isz) / 0.05039;
+    if (wse > 40.0) {
+        wse = (isf < 0.999 * 2.496 * ff) ? 28.0 - log(1.0 - isf / (2.496 * ff)) / 0.0818 : 112.45;
+    }
+    return wse;
+}
+
+// Head and back rates, length-to-breadth ratio and the effective wind
+// vector (east, north components; its direction is the head direction).
+template <typename R>
+struct CellRates {
+    R h, b, lb, lbm1, wx, wy, wsv;   // lbm1 = LB - 1, kept separately for accuracy
+};
+
+// Everything is evaluated in R except the slope-equivalent wind, which is
+// FP64 in both modes: inverting the rate curve near its asymptote (the
+// WSE > 40 branch) turns a relative error of 1e-7 in ISF into ~1e-4 in WSE.
+// row64 is the FP64 weather row of the same (scenario, period).
+template <typename R>
+__device__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64, int f, int gx,
+                                   int gn, const R* row, const double* row64, const LandR<R>& L,
+                                   const LandR<double>& L64) {
+    R wx = row[2], wy = row[3];
+    if ((gx | gn) != 0) {
+        const double g = sqrt((double)gx * (double)gx + (double)gn * (double)gn);
+        const double gs = 100.0 * g / (8.0 * L64.cell_m);                  // slope, percent
+        const double sf = (gs >= 70.0) ? 10.0 : exp(3.533 * pow(gs / 100.0, 1.2));
+        const double wse = slope_wind(coef64, f, sf, row64, L64);
+        wx += (R)(wse * ((double)gx / g));                                 // along the upslope unit vector
+        wy += (R)(wse * ((double)gn / g));
+    }
+    const R wsv = m_sqrt(wx * wx + wy * wy);
+    const R fw = (wsv <= (R)40) ? m_exp((R)0.05039 * wsv)
+                                : (R)12 * -m_expm1((R)-0.0818 * (wsv - (R)28));
+    const R be = row[kRowBE + f];
+    const R isz = row[1];
+    CellRates<R> out;
+    out.h = rsi_fuel(coef, f, isz * fw, L) * be;
+    out.b = rsi_fuel(coef, f, isz * m_exp((R)-0.05039 * wsv), L) * be;
+    if (f >= kO1a) out.lbm1 = (wsv >= (R)1) ? (R)1.1 * m_pow(wsv, (R)0.464) - (R)1 : (R)0;
+    else out.lbm1 = (R)8.729 * m_pow(-m_expm1((R)-0.030 * wsv), (R)2.155);
+    out.lb = (R)1 + out.lbm1;
+    out.wx = wx;
+    out.wy = wy;
+    out.wsv = wsv;
+    return out;
+}
+
+// Lognormal rate multiplier with mean 1 for (cell, period, rep).
+template <typename R>
+__device__ __forceinline__ R noise_mult(uint64_t seed, uint32_t cell, uint32_t period, uint32_t rep,
+                                        R sigma) {
+    if (sigma == (R)0) return (R)1;
+    const uint4 x = draw(seed, cell, period, rep, 0u);
+    const R u1 = ((R)(x.x >> 8) + (R)1) * (R)(1.0 / 16777216.0);
+    const R u2 = unit24<R>(x.y);
+    const R z = m_sqrt((R)-2 * m_log(u1)) * m_cos((R)2 * Const<R>::pi * u2);
+    return m_exp(sigma * z - (R)0.5 * sigma * sigma);
+}
+
+// Directional rates along the 8 axes (eq. (1)): with a = (H+B)/2 (eq. (2)),
+// e^2 = 1 - 1/LB^2 (eq. (4) with FROS = a/LB), cos(phi) the cosine between
+// the axis and the head direction, the front half (cos phi > 0) spreads at
+// a(1-e^2)/(1 - e cos phi) and the back half at a(1-e^2).  Each rate is then
+// scaled by the noise multiplier mu.  e is formed from LB - 1 directly and
+// the denominator is evaluated as (1 - e) + e (1 - cos phi) with
+// 1 - e = LB^-2 / (1 + e) and
+// 1 - cos phi = |w/|w| - u|^2 / 2, which avoids the cancellation of
+// 1 - e cos phi near the head direction when LB is large.
+template <typename R>
+__device__ __forceinline__ void axis_rates(const CellRates<R>& cr, R mu, R* x8) {
+    const R a = (R)0.5 * (cr.h + cr.b);
+    const R il = (R)1 / cr.lb;
+    const R il2 = il * il;
+    const R base = a * il2;                           // a (1 - e^2)
+    const R e = m_sqrt(cr.lbm1 * (cr.lbm1 + (R)2)) * il;   // sqrt(1 - 1/LB^2)
+    const R one_m_e = il2 / ((R)1 + e);
+    const R inv_wsv = (cr.wsv > (R)0) ? (R)1 / cr.wsv : (R)0;
+    const R cx = cr.wx * inv_wsv, cy = cr.wy * inv_wsv;   // unit head direction
+    const R s = (R)0.70710678118654752440;
+    const R ux[8] = {(R)1, s, (R)0, -s, (R)-1, -s, (R)0, s};
+    const R uy[8] = {(R)0, s, (R)1, s, (R)0, -s, (R)-1, -s};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const R c = ux[k] * cx + uy[k] * cy;
+        R r = base;
+        if (c > (R)0) {
+            const R dx = cx - ux[k], dy = cy - uy[k];
+            r = base / (one_m_e + e * ((R)0.5 * (dx * dx + dy * dy)));
+        }
+        x8[k] = mu * r;
+    }
+}
+
+}  // namespace c2f

@@ -1,0 +1,32 @@
+// Host-side launchers of the gfx950 kernels (internal to libc2f).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "types.h"
+
+namespace c2f {
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_bytes(void* p, size_t bytes, uint8_t v, hipStream_t s);
+
+// Horn gradients, burnable list, nearest-centre cell and landscape constants.
+// tile_scratch holds tile_scratch_entries(rows*cols) int32.
+hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, int rows, int cols,
+                                    int cell_m, float pc, float curing, uint32_t* grad,
+                                    int32_t* burnable, int32_t* tile_scratch, LandDev* land,
+                                    hipStream_t s);
+int64_t tile_scratch_entries(int64_t n_cells);
+
+// Per (scenario, period) weather terms in FP64 and FP32; wx is [n_rows][4].
+hipError_t launch_weather_table(const float* wx, int n_rows, double* t64, float* t32, hipStream_t s);
+
+hipError_t launch_eval_ros(int precision, const EvalArgs& a, hipStream_t s);
+
+// Persistent propagation over `total` work items (one per replication).
+hipError_t launch_propagate(int precision, int block, int grid, const Job* jobs, int n_jobs, int total,
+                            const Slots& slots, RunCounters* rc, hipStream_t s);
+int propagate_blocks_per_cu(int precision, int block);
+
+}  // namespace c2f

@@ -1,0 +1,88 @@
+"""Shared helpers for the GPU parity tests (not collected by pytest)."""
+import numpy as np
+
+import oracle
+from paper_1905_09317_amd import Request
+
+OUTS = ("scar", "arrival_period", "arrival_minute", "burn_count", "burned_cells", "ignition_cell",
+        "scenario")
+
+
+def oracle_run(fuel, elev, weather, *, n_periods, reps=1, rep_offset=0, seed=0, sigma=0.0,
+               threshold=0.0, rounding=0, ignition_mode=0, ignition_cell=0, scenario_mode=0,
+               scenario=0, period_min=60, cell_m=100, pc=50.0, curing=80.0, overrides=None,
+               want_rep_outputs=True):
+    return oracle.simulate(fuel, elev, weather, cell_m=cell_m, n_periods=n_periods, reps=reps,
+                           rep_offset=rep_offset, seed=seed, sigma=np.float32(sigma).item(),
+                           threshold=np.float32(threshold).item(), rounding=rounding,
+                           ignition_mode=ignition_mode, ignition_cell=ignition_cell,
+                           scenario_mode=scenario_mode, scenario=scenario, period_min=period_min,
+                           pc=np.float32(pc).item(), curing=np.float32(curing).item(),
+                           overrides=overrides, want_rep_outputs=want_rep_outputs)
+
+
+def assert_same_outputs(gpu: dict, ref: dict, names=OUTS, where=""):
+    for k in names:
+        if k not in gpu:
+            continue
+        g = np.asarray(gpu[k])
+        r = np.asarray(ref[k])
+        if k == "burn_count":
+            g = g.view(np.uint32) if g.dtype == np.int32 else g
+        assert g.shape == r.shape, (where, k, g.shape, r.shape)
+        if not np.array_equal(g, r):
+            bad = np.argwhere(g != r)
+            first = tuple(bad[0])
+            raise AssertionError(f"{where} {k}: {len(bad)} mismatches, first at {first}: "
+                                 f"gpu={g[first]} oracle={r[first]}")
+
+
+def request_kwargs(w, **over):
+    kw = dict(n_periods=w.n_periods, reps=w.reps, seed=w.seed, sigma=w.sigma,
+              threshold=w.threshold, rounding=w.rounding, precision=w.precision,
+              ignition_mode=w.ignition_mode, ignition_cell=w.ignition_cell,
+              scenario_mode=w.scenario_mode, scenario=w.scenario)
+    kw.update(over)
+    return kw
+
+
+def oracle_kwargs(w, **over):
+    kw = dict(n_periods=w.n_periods, reps=w.reps, seed=w.seed, sigma=w.sigma,
+              threshold=w.threshold, rounding=w.rounding, ignition_mode=w.ignition_mode,
+              ignition_cell=w.ignition_cell, scenario_mode=w.scenario_mode, scenario=w.scenario,
+              period_min=w.period_min, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    kw.update(over)
+    kw.pop("precision", None)
+    return kw
+
+
+def boundary_case(xu: np.ndarray, x: np.ndarray, tol_rel: float) -> np.ndarray:
+    """True where the oracle's floored value sits within tol of an integer."""
+    return np.abs(xu - np.rint(xu)) <= tol_rel * np.maximum(1.0, np.abs(x))
+
+
+def fp32_overrides(sim, land, wx, fuel, elev, weather, *, reps, n_periods, seed, sigma, rounding,
+                   scenarios, cell_m=100, pc=50.0, curing=80.0, tol_rel=2e-5):
+    """Audit FP32 integer rates against the FP64 oracle for every (rep, period)
+    and return (override keys, q) for the cells where they differ; every
+    difference must be a boundary case of the oracle's value."""
+    keys, qs, n_checked = [], [], 0
+    for r in range(reps):
+        for p in range(n_periods):
+            g = sim.eval_ros(land, wx, scenario=int(scenarios[r]), period=p, rep=r, seed=seed,
+                             sigma=sigma, rounding=rounding, precision=1)
+            o = oracle.eval_ros(fuel, elev, weather, cell_m=cell_m, scenario=int(scenarios[r]),
+                                period=p, rep=r, seed=seed, sigma=np.float32(sigma).item(),
+                                rounding=rounding, pc=pc, curing=curing)
+            diff = np.any(g["q8"] != o["q8"], axis=1)
+            n_checked += g["q8"].size
+            if diff.any():
+                cells = np.nonzero(diff)[0]
+                ok = boundary_case(o["xu8"][cells], o["x8"][cells], tol_rel) | (g["q8"][cells] == o["q8"][cells])
+                assert ok.all(), f"rep {r} period {p}: non-boundary integer-rate mismatch at cells {cells[~ok.all(axis=1)][:5]}"
+                for c in cells:
+                    keys.append((r, p, int(c)))
+                    qs.append(g["q8"][c])
+    k = np.array(keys, np.int32).reshape(-1, 3)
+    q = np.array(qs, np.int32).reshape(-1, 8)
+    return k, q, n_checked

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point of include/c2f.h
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1905_09317_amd import _lib, fbp_coefficients
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "c2f.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(c2f_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(_lib.DECLARED) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    lib2 = ctypes.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        getattr(lib2, name)
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(_lib.SimParams) == 4 * 4 + 8 + 4 * 2 + 4 * 7 + 4   # padded to 8
+    assert ctypes.sizeof(_lib.Outputs) == 7 * 8 + 8
+    assert ctypes.sizeof(_lib.WeatherRow) == 16
+
+
+@pytest.mark.parametrize("fuel", range(1, 16))
+def test_device_fuel_table_equals_oracle_table(fuel):
+    assert np.array_equal(fbp_coefficients(fuel), oracle.fuel_coefficients(fuel))
+
+
+def test_bad_fuel_code_rejected():
+    with pytest.raises(Exception):
+        fbp_coefficients(0)
+    with pytest.raises(Exception):
+        fbp_coefficients(16)
+
+
+def test_create_without_gpu_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    lib = _lib.load()
+    ctx = ctypes.c_void_p()
+    st = lib.c2f_create(0, 0, ctypes.byref(ctx))
+    assert st == _lib.C2F_EDEVICE and not ctx.value
+    assert lib.c2f_last_error(None) == b"null context"
