@@ -191,6 +191,8 @@ typedef struct {
     int64_t candidates;      /* arrival candidates offered to neighbours */
     int64_t improvements;    /* candidates that lowered an arrival */
     int64_t relaunches;      /* repeats after a work-list overflow */
+    int64_t rounds;          /* label-correcting rounds, summed over reps */
+    int64_t continuations;   /* period-boundary continuations read */
     double kernel_ms;        /* propagation kernel time (HIP events) */
     int32_t block_threads, grid_blocks;
     int64_t list_capacity;

@@ -40,6 +40,7 @@ class RunStats(ctypes.Structure):
     _fields_ = [("ignitions", ctypes.c_int64), ("entries", ctypes.c_int64),
                 ("rate_evals", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("improvements", ctypes.c_int64), ("relaunches", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("continuations", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("block_threads", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
 

@@ -34,11 +34,11 @@ struct Landscape {
     int32_t rows = 0, cols = 0, cell_m = 0;
     float pc = 50.f, curing = 80.f;
     uint8_t* fuel = nullptr;
-    uint32_t* grad = nullptr;
+    CellRec* cells = nullptr;
     int32_t* burnable = nullptr;
     LandDev* land = nullptr;
     size_t bytes = 0;
-    int64_t cells() const { return (int64_t)rows * cols; }
+    int64_t ncells() const { return (int64_t)rows * cols; }
 };
 
 struct Weather {
@@ -97,7 +97,7 @@ struct c2f_ctx {
     uint32_t* planes = nullptr;
     int64_t plane_cells = 0;
     int32_t n_slots = 0;
-    uint2* lists = nullptr;
+    uint8_t* lists = nullptr;
     int64_t list_cap = 0;
     int32_t list_slots = 0;
     uint32_t* tags = nullptr;
@@ -239,12 +239,12 @@ c2f_status ensure_slots(c2f_ctx* ctx, int32_t n, int64_t cells, int64_t cap) {
     }
     if (n > ctx->list_slots || cap != ctx->list_cap) {
         drop_graph(ctx);
-        dev_free(ctx, ctx->lists, (size_t)ctx->list_slots * 4 * ctx->list_cap * sizeof(uint2));
+        dev_free(ctx, ctx->lists, (size_t)ctx->list_slots * ctx->list_cap * kSlotListBytesPerEntry);
         ctx->lists = nullptr;
         const int32_t ns = std::max(n, ctx->list_slots);
         ctx->list_slots = 0;
         ctx->list_cap = 0;
-        c2f_status st = dev_alloc(ctx, (void**)&ctx->lists, (size_t)ns * 4 * cap * sizeof(uint2));
+        c2f_status st = dev_alloc(ctx, (void**)&ctx->lists, (size_t)ns * cap * kSlotListBytesPerEntry);
         if (st != C2F_OK) return st;
         ctx->list_slots = ns;
         ctx->list_cap = cap;
@@ -309,7 +309,7 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, const Landscape**
     if (p->rounding != 0 && p->rounding != 1) return fail(ctx, C2F_EINVAL, "rounding must be 0 or 1");
     if (p->precision != 0 && p->precision != 1) return fail(ctx, C2F_EINVAL, "precision must be 0 or 1");
     if (p->ignition_mode < 0 || p->ignition_mode > 2) return fail(ctx, C2F_EINVAL, "ignition_mode must be 0..2");
-    if (p->ignition_mode == 0 && (p->ignition_cell < 0 || p->ignition_cell >= l.cells()))
+    if (p->ignition_mode == 0 && (p->ignition_cell < 0 || p->ignition_cell >= l.ncells()))
         return fail(ctx, C2F_EINVAL, "ignition_cell %d outside the grid", p->ignition_cell);
     if (p->scenario_mode < 0 || p->scenario_mode > 1) return fail(ctx, C2F_EINVAL, "scenario_mode must be 0 or 1");
     if (p->scenario_mode == 0 && (p->scenario < 0 || p->scenario >= w.n_scen))
@@ -360,7 +360,7 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
     int64_t max_cells = 0;
     int32_t total = 0;
     for (int k : idx) {
-        max_cells = std::max(max_cells, Ls[k]->cells());
+        max_cells = std::max(max_cells, Ls[k]->ncells());
         total += P[k].reps;
     }
     LaunchPlan lp = plan_launch(ctx, max_cells, total, precision);
@@ -385,8 +385,7 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
             const OutPlan& o = plans[k];
             Job j;
             memset(&j, 0, sizeof j);
-            j.fuel = L.fuel;
-            j.grad = L.grad;
+            j.cells = L.cells;
             j.burnable = L.burnable;
             j.land = L.land;
             j.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
@@ -433,7 +432,7 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
                                      (uint64_t)(uintptr_t)ctx->stream};
         for (int k : idx) {
             key.push_back((uint64_t)(uintptr_t)plans[k].count);
-            key.push_back((uint64_t)Ls[k]->cells());
+            key.push_back((uint64_t)Ls[k]->ncells());
         }
         // fills + propagation; the events bracket this sequence (they are
         // recorded outside any graph capture)
@@ -442,7 +441,7 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
             if (e != hipSuccess) return e;
             for (int k : idx) {
                 if (plans[k].count) {
-                    e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->cells(), 0u, ctx->stream);
+                    e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->ncells(), 0u, ctx->stream);
                     if (e != hipSuccess) return e;
                 }
             }
@@ -494,6 +493,8 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
             ctx->last.candidates += (int64_t)ctx->rc_host->c[kCntCandidates];
             ctx->last.improvements += (int64_t)ctx->rc_host->c[kCntImprovements];
             ctx->last.ignitions += (int64_t)ctx->rc_host->c[kCntIgnitions];
+            ctx->last.rounds += (int64_t)ctx->rc_host->c[kCntRounds];
+            ctx->last.continuations += (int64_t)ctx->rc_host->c[kCntConts];
             ctx->last.block_threads = lp.block;
             ctx->last.grid_blocks = lp.grid;
             ctx->last.list_capacity = lp.cap;
@@ -536,7 +537,7 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
     for (int k = 0; k < n_jobs; ++k) {
         const c2f_outputs& o = outs[k];
         plans[k].user = o;
-        const size_t n = (size_t)Ls[k]->cells(), r = (size_t)P[k].reps;
+        const size_t n = (size_t)Ls[k]->ncells(), r = (size_t)P[k].reps;
         if (o.on_device) {
             plans[k].scar = o.scar;
             plans[k].arr_period = o.arrival_period;
@@ -579,7 +580,7 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
     for (int k = 0; k < n_jobs; ++k) {
         const c2f_outputs& o = outs[k];
         if (o.on_device) continue;
-        const size_t n = (size_t)Ls[k]->cells(), r = (size_t)P[k].reps;
+        const size_t n = (size_t)Ls[k]->ncells(), r = (size_t)P[k].reps;
         auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
             if (!dst) return hipSuccess;
             return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream);
@@ -599,7 +600,7 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
 size_t request_footprint(const c2f_ctx* ctx, const c2f_sim_params& p) {
     auto li = ctx->lands.find(p.landscape_id);
     if (li == ctx->lands.end()) return 0;
-    const size_t n = (size_t)li->second.cells();
+    const size_t n = (size_t)li->second.ncells();
     // staging of the outputs the serving path may return (counts + per-rep)
     return n * 4 + (size_t)p.reps * 24;
 }
@@ -652,7 +653,7 @@ void c2f_destroy(c2f_ctx* ctx) {
     drop_graph(ctx);
     for (auto& kv : ctx->lands) {
         (void)hipFree(kv.second.fuel);
-        (void)hipFree(kv.second.grad);
+        (void)hipFree(kv.second.cells);
         (void)hipFree(kv.second.burnable);
         (void)hipFree(kv.second.land);
     }
@@ -714,14 +715,14 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     c2f_status st = C2F_OK;
     auto cleanup = [&]() {
         dev_free(ctx, L.fuel, (size_t)n);
-        dev_free(ctx, L.grad, (size_t)n * 4);
+        dev_free(ctx, L.cells, (size_t)n * sizeof(CellRec));
         dev_free(ctx, L.burnable, (size_t)n * 4);
         dev_free(ctx, L.land, sizeof(LandDev));
         dev_free(ctx, d_elev, (size_t)n * 2);
         dev_free(ctx, d_tiles, (size_t)n_tiles * 4);
     };
     if ((st = dev_alloc(ctx, (void**)&L.fuel, (size_t)n)) != C2F_OK ||
-        (st = dev_alloc(ctx, (void**)&L.grad, (size_t)n * 4)) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&L.cells, (size_t)n * sizeof(CellRec))) != C2F_OK ||
         (st = dev_alloc(ctx, (void**)&L.burnable, (size_t)n * 4)) != C2F_OK ||
         (st = dev_alloc(ctx, (void**)&L.land, sizeof(LandDev))) != C2F_OK ||
         (st = dev_alloc(ctx, (void**)&d_tiles, (size_t)n_tiles * 4)) != C2F_OK ||
@@ -732,7 +733,7 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     hipError_t e = hipMemcpyAsync(L.fuel, fuel, (size_t)n, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess && elev_m) e = hipMemcpyAsync(d_elev, elev_m, (size_t)n * 2, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
-        e = launch_prepare_landscape(L.fuel, d_elev, rows, cols, cell_m, pc_pct, curing_pct, L.grad, L.burnable,
+        e = launch_prepare_landscape(L.fuel, d_elev, rows, cols, cell_m, pc_pct, curing_pct, L.cells, L.burnable,
                                      d_tiles, L.land, ctx->stream);
     LandDev hl;
     if (e == hipSuccess) e = hipMemcpyAsync(&hl, L.land, sizeof hl, hipMemcpyDeviceToHost, ctx->stream);
@@ -749,7 +750,7 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
         cleanup();
         return fail(ctx, C2F_EINVAL, "elevation too steep: a Horn gradient numerator exceeds 32767");
     }
-    L.bytes = (size_t)n * 9 + sizeof(LandDev);
+    L.bytes = (size_t)n * (1 + sizeof(CellRec) + 4) + sizeof(LandDev);
     const int32_t id = ctx->next_id++;
     ctx->lands[id] = L;
     *landscape_id = id;
@@ -765,9 +766,9 @@ c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id) {
     (void)hipStreamSynchronize(ctx->stream);
     drop_graph(ctx);
     Landscape& L = it->second;
-    const size_t n = (size_t)L.cells();
+    const size_t n = (size_t)L.ncells();
     dev_free(ctx, L.fuel, n);
-    dev_free(ctx, L.grad, n * 4);
+    dev_free(ctx, L.cells, n * sizeof(CellRec));
     dev_free(ctx, L.burnable, n * 4);
     dev_free(ctx, L.land, sizeof(LandDev));
     ctx->lands.erase(it);
@@ -876,15 +877,14 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
         (precision != 0 && precision != 1))
         return fail(ctx, C2F_EINVAL, "bad sigma/rounding/precision");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    const size_t n = (size_t)L.cells();
+    const size_t n = (size_t)L.ncells();
     const size_t bytes = n * 8 * 5 + n * 64 + n * 32 + 7 * 256;   // 7 arrays, 256-byte aligned
     c2f_status st = ensure_staging(ctx, bytes);
     if (st != C2F_OK) return st;
     char* sb = (char*)ctx->staging;
     EvalArgs a;
     memset(&a, 0, sizeof a);
-    a.fuel = L.fuel;
-    a.grad = L.grad;
+    a.cells = L.cells;
     a.land = L.land;
     a.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
     a.table64 = W.t64;
@@ -956,7 +956,7 @@ c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* rep) {
     c2f_status st = check_params(ctx, rep, &L, &W);
     if (st != C2F_OK) return st;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    const int64_t n = L->cells();
+    const int64_t n = L->ncells();
     uint32_t* counts = nullptr;
     st = dev_alloc(ctx, (void**)&counts, (size_t)n * 4);
     if (st != C2F_OK) return st;

@@ -168,16 +168,15 @@ struct CellRates {
 // Everything is evaluated in R except the slope-equivalent wind, which is
 // FP64 in both modes: inverting the rate curve near its asymptote (the
 // WSE > 40 branch) turns a relative error of 1e-7 in ISF into ~1e-4 in WSE.
-// row64 is the FP64 weather row of the same (scenario, period).
+// row64 is the FP64 weather row of the same (scenario, period); sf is the
+// cell's slope factor (a static property of the cell).
 template <typename R>
-__device__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64, int f, int gx,
-                                   int gn, const R* row, const double* row64, const LandR<R>& L,
+__device__ __noinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64, int f, int gx,
+                                   int gn, double sf, const R* row, const double* row64, const LandR<R>& L,
                                    const LandR<double>& L64) {
     R wx = row[2], wy = row[3];
     if ((gx | gn) != 0) {
         const double g = sqrt((double)gx * (double)gx + (double)gn * (double)gn);
-        const double gs = 100.0 * g / (8.0 * L64.cell_m);                  // slope, percent
-        const double sf = (gs >= 70.0) ? 10.0 : exp(3.533 * pow(gs / 100.0, 1.2));
         const double wse = slope_wind(coef64, f, sf, row64, L64);
         wx += (R)(wse * ((double)gx / g));                                 // along the upslope unit vector
         wy += (R)(wse * ((double)gn / g));
@@ -198,6 +197,19 @@ __device__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* co
     out.wsv = wsv;
     return out;
 }
+
+// FBP slope factor of a cell from its Horn numerators: SF = exp(3.533
+// (GS/100)^1.2) with GS = 100 |g| / (8 cs) percent, capped at 10 from 70 %.
+__device__ __forceinline__ double slope_factor(int gx, int gn, double cell_m) {
+    if ((gx | gn) == 0) return 1.0;
+    const double gs = 100.0 * sqrt((double)gx * (double)gx + (double)gn * (double)gn) / (8.0 * cell_m);
+    return (gs >= 70.0) ? 10.0 : exp(3.533 * pow(gs / 100.0, 1.2));
+}
+
+__device__ __forceinline__ int rec_fuel(uint32_t info) { return (int)(info & 0xFFu); }
+__device__ __forceinline__ uint32_t rec_nbmask(uint32_t info) { return (info >> 8) & 0xFFu; }
+__device__ __forceinline__ int rec_gx(uint32_t g) { return (int)(int16_t)(g & 0xFFFFu); }
+__device__ __forceinline__ int rec_gn(uint32_t g) { return (int)(int16_t)(g >> 16); }
 
 // Lognormal rate multiplier with mean 1 for (cell, period, rep).
 template <typename R>
@@ -243,6 +255,80 @@ __device__ __forceinline__ void axis_rates(const CellRates<R>& cr, R mu, R* x8) 
         }
         x8[k] = mu * r;
     }
+}
+
+}  // namespace c2f
+
+namespace c2f {
+
+// FBP coefficient tables in each translation unit's constant memory.
+static __constant__ CoefR<double> kCoef64[kNumFuels] = {C2F_FUEL_ROWS};
+static __constant__ CoefR<float> kCoef32[kNumFuels] = {C2F_FUEL_ROWS};
+
+template <typename R> __device__ __forceinline__ const CoefR<R>* coef_table();
+template <> __device__ __forceinline__ const CoefR<double>* coef_table<double>() { return kCoef64; }
+template <> __device__ __forceinline__ const CoefR<float>* coef_table<float>() { return kCoef32; }
+
+template <typename R> __device__ __forceinline__ LandR<R> land_consts(const LandDev* L);
+template <> __device__ __forceinline__ LandR<double> land_consts<double>(const LandDev* L) {
+    return LandR<double>{L->pc_w64, L->cf64, L->cell_m64};
+}
+template <> __device__ __forceinline__ LandR<float> land_consts<float>(const LandDev* L) {
+    return LandR<float>{L->pc_w32, L->cf32, L->cell_m32};
+}
+
+// Everything a rate evaluation needs besides the cell: coefficient tables,
+// landscape constants, the scenario's weather rows and the random stream.
+template <typename R>
+struct RateCtx {
+    const CoefR<R>* coef;
+    const CoefR<double>* coef64;
+    LandR<R> L;
+    LandR<double> L64;
+    const R* rows;          // first row of the replication's scenario
+    const double* rows64;
+    uint64_t seed;
+    R sigma;
+    int rounding;
+    uint32_t rep;
+};
+
+// Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
+// the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.
+template <typename R>
+__device__ __forceinline__ void axis_q(const RateCtx<R>& X, uint32_t info, uint32_t grad, double sf,
+                                       uint32_t cell, uint32_t period, int32_t* q) {
+    const size_t ro = (size_t)period * kRowLen;
+    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec_fuel(info), rec_gx(grad), rec_gn(grad), sf,
+                                          X.rows + ro, X.rows64 + ro, X.L, X.L64);
+    const R mu = noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
+    R x[8];
+    axis_rates<R>(cr, mu, x);
+    R u[8];
+    if (X.rounding == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) u[k] = (R)0.5;
+    } else {
+        const uint4 a = draw(X.seed, cell, period, X.rep, 1u);
+        const uint4 b = draw(X.seed, cell, period, X.rep, 2u);
+        u[0] = unit24<R>(a.x); u[1] = unit24<R>(a.y); u[2] = unit24<R>(a.z); u[3] = unit24<R>(a.w);
+        u[4] = unit24<R>(b.x); u[5] = unit24<R>(b.y); u[6] = unit24<R>(b.z); u[7] = unit24<R>(b.w);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const R v = m_floor(x[k] + u[k]);
+        q[k] = (v < (R)1073741824) ? (int32_t)v : 1073741824;
+    }
+}
+
+// Head rate times the noise multiplier: the receiving cell's ignition test.
+template <typename R>
+__device__ __forceinline__ R head_rate(const RateCtx<R>& X, uint32_t info, uint32_t grad, double sf,
+                                       uint32_t cell, uint32_t period) {
+    const size_t ro = (size_t)period * kRowLen;
+    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec_fuel(info), rec_gx(grad), rec_gn(grad), sf,
+                                          X.rows + ro, X.rows64 + ro, X.L, X.L64);
+    return cr.h * noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
 }
 
 }  // namespace c2f

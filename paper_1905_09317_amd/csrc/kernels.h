@@ -9,12 +9,11 @@
 namespace c2f {
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
-hipError_t launch_fill_bytes(void* p, size_t bytes, uint8_t v, hipStream_t s);
 
-// Horn gradients, burnable list, nearest-centre cell and landscape constants.
+// Cell records, burnable list, nearest-centre cell and landscape constants.
 // tile_scratch holds tile_scratch_entries(rows*cols) int32.
 hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, int rows, int cols,
-                                    int cell_m, float pc, float curing, uint32_t* grad,
+                                    int cell_m, float pc, float curing, CellRec* recs,
                                     int32_t* burnable, int32_t* tile_scratch, LandDev* land,
                                     hipStream_t s);
 int64_t tile_scratch_entries(int64_t n_cells);

@@ -1,0 +1,484 @@
+// The persistent fire-growth kernel.
+//
+// Model (Sections 3.1 and 3.4, Algorithm 1 Step 2).  Once a cell ignites at
+// minute a, its fire advances q_k(p) metres along axis k in each later minute
+// of period p (the FBP rates of the cell in that period through eq. (1)),
+// and reaches neighbour k once the distance D_k between the two centres is
+// covered.  The neighbour ignites in that minute if its own head rate passes
+// the threshold, else at the start of the first later period that passes
+// (the message persists).  Every hop takes at least one minute and rates do
+// not depend on the order of ignitions, so the arrival minutes are the least
+// solution of arrival(j) = min_i accept_j(reach_ij(arrival(i))): any
+// evaluation order that only commits arrivals of the current period and
+// carries per-axis progress across period ends gives exactly the minute-
+// stepping result.
+//
+// Work decomposition.  One work group per replication (persistent groups
+// take replications from a counter).  Per weather period p:
+//   - cells waiting for a passing rate (pending) are re-tested;
+//   - cells whose axes were still travelling at the end of p-1
+//     (continuations, with the metres left on each axis) are advanced
+//     through p;
+//   - label-correcting rounds: each cell that received a smaller arrival
+//     in p is advanced from that minute to the end of p.
+// Advancing a cell through a period costs one FBP evaluation; axes that
+// reach their neighbour inside p offer that minute with atomicMin on the
+// neighbour's 32-bit label, the rest become a continuation for p+1.  Round
+// lists live in LDS (spilling to the slot's global lists), appended with a
+// wave ballot and prefix count and one LDS atomic per wave.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+#include "kernels.h"
+#include "types.h"
+
+namespace c2f {
+
+constexpr int32_t kNever = 0x7FFFFFFF;
+
+__device__ __forceinline__ uint32_t load_label(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int wave_rank(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One LDS atomic per wave reserves slots for the appending lanes.
+__device__ __forceinline__ int wave_reserve(bool pred, int* counter, uint64_t& m) {
+    m = __ballot(pred);
+    if (m == 0) return 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (__lane_id() == leader) base = atomicAdd(counter, (int)__popcll(m));
+    return __shfl(base, leader) + wave_rank(m);
+}
+
+// Round lists: the first lcap entries in LDS, the rest in the slot's global list.
+__device__ __forceinline__ void append_w(bool pred, uint2 val, uint2* lds, int lcap, uint2* glob, int64_t cap,
+                                         int* counter, int* flag) {
+    uint64_t m;
+    const int idx = wave_reserve(pred, counter, m);
+    if (pred) {
+        if (idx < lcap) lds[idx] = val;
+        else if ((int64_t)(idx - lcap) < cap) glob[idx - lcap] = val;
+        else *flag = 1;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void append_g(bool pred, const T& val, T* glob, int64_t cap, int* counter, int* flag) {
+    uint64_t m;
+    const int idx = wave_reserve(pred, counter, m);
+    if (pred) {
+        if ((int64_t)idx < cap) glob[idx] = val;
+        else *flag = 1;
+    }
+}
+
+// Advance cell c (label lab) through period p from minute m0 to e.  rem[k]
+// holds the metres left on axis k (0 = done).  On return cand[k] is the
+// minute the fire reaches neighbour k inside p (or kNever) and rem[] the
+// metres left at the end of p for axes still worth following.  An axis is
+// dropped once its neighbour already holds a label no later candidate can
+// beat, or is pending (its ignition minute is then already determined).
+template <typename R>
+__device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, uint32_t c, int p, int32_t m0,
+                                       int32_t e, const uint32_t* __restrict__ plane, uint32_t tag,
+                                       const int32_t* off, int32_t* rem, int32_t* cand) {
+    const uint32_t nb = rec_nbmask(rec.info);
+    int32_t curv[8];
+    uint32_t live = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        cand[k] = kNever;
+        curv[k] = kNever;
+        if (!((nb >> k) & 1u) || rem[k] <= 0) {
+            rem[k] = 0;
+            continue;
+        }
+        const uint32_t v = plane[(int64_t)c + off[k]];
+        if ((v >> kMinuteBits) == tag) {
+            const int32_t t = (int32_t)(v & kMinuteMask);
+            if (t == (int32_t)kPendingMinute || t <= m0) {
+                rem[k] = 0;
+                continue;
+            }
+            curv[k] = t;
+        }
+        live |= 1u << k;
+    }
+    int evals = 0;
+    if (live != 0u && m0 <= e) {
+        int32_t q[8];
+        axis_q<R>(X, rec.info, rec.grad, rec.sf, c, (uint32_t)p, q);
+        evals = 1;
+        const int64_t n = (int64_t)(e - m0 + 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (!((live >> k) & 1u)) continue;
+            const int32_t qk = q[k];
+            if (qk > 0 && (int64_t)qk * n >= rem[k]) {
+                cand[k] = m0 + (rem[k] + qk - 1) / qk - 1;
+                rem[k] = 0;
+            } else {
+                rem[k] -= (int32_t)((int64_t)qk * n);
+                if (curv[k] <= e + 1) rem[k] = 0;   // nothing after p can beat it
+            }
+        }
+    }
+    return evals;
+}
+
+// At least 4 waves per SIMD (<= 128 VGPRs): the kernel is latency bound,
+// so resident replications matter more than registers.
+template <typename R, int BLOCK>
+__global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restrict__ jobs, int n_jobs,
+                                                          int total_items, Slots slots,
+                                                          RunCounters* __restrict__ rc) {
+    constexpr int LCAP = BLOCK <= 64 ? 512 : (BLOCK <= 128 ? 1024 : (BLOCK <= 256 ? 2048 : 4096));
+    __shared__ uint2 s_W[2][LCAP];
+    __shared__ int s_nW[2], s_nC[2], s_nP[2];
+    __shared__ int s_item, s_flag;
+    __shared__ uint32_t s_tag;
+    __shared__ int s_scen, s_ign;
+    __shared__ unsigned long long s_cnt[kNumCounters];
+    __shared__ CoefR<R> s_coef[kNumFuels];
+    __shared__ CoefR<double> s_coef64[kNumFuels];
+
+    const int tid = threadIdx.x;
+    const int slot = blockIdx.x;
+    if (tid < kNumFuels) {
+        s_coef[tid] = coef_table<R>()[tid];
+        s_coef64[tid] = coef_table<double>()[tid];
+    }
+    uint32_t* __restrict__ plane = slots.planes + (size_t)slot * (size_t)slots.plane_cells;
+    const int64_t cap = slots.list_cap;
+    uint8_t* lb = slots.lists + (size_t)slot * (size_t)cap * (size_t)kSlotListBytesPerEntry;
+    uint2* const gW[2] = {(uint2*)lb, (uint2*)lb + cap};
+    Cont* const gC[2] = {(Cont*)(lb + 16 * cap), (Cont*)(lb + 16 * cap) + cap};
+    uint32_t* const gP[2] = {(uint32_t*)(lb + 64 * cap), (uint32_t*)(lb + 64 * cap) + cap};
+
+    for (;;) {
+        if (tid == 0) {
+            int it = atomicAdd(&rc->next_item, 1);
+            if (__hip_atomic_load(&rc->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total_items;
+            s_item = it;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total_items) break;
+
+        // job lookup (jobs are sorted by item_base)
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].item_base <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const Job& job = jobs[lo];
+        const int lr = item - job.item_base;
+        const uint32_t rep = (uint32_t)(job.rep_offset + lr);
+        const int cols = job.cols;
+        const int P = job.period_min;
+        const CellRec* __restrict__ cells = job.cells;
+        const bool use_thr = job.threshold > 0.0f;
+        const R thr = (R)job.threshold;
+        const int32_t D[8] = {job.d_orth, job.d_diag, job.d_orth, job.d_diag,
+                              job.d_orth, job.d_diag, job.d_orth, job.d_diag};
+        const int32_t off[8] = {1, 1 - cols, -cols, -cols - 1, -1, cols - 1, cols, cols + 1};
+
+        // ------------------------------------------- replication set-up
+        if (tid == 0) {
+            s_tag = slots.tags[slot];   // previous tag; refilled below if exhausted
+            s_nW[0] = s_nW[1] = s_nC[0] = s_nC[1] = s_nP[0] = s_nP[1] = 0;
+            s_flag = 0;
+            for (int k = 0; k < kNumCounters; ++k) s_cnt[k] = 0;
+            int scen = job.scen_fixed;
+            if (job.scen_mode == 1) {
+                const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 4u);
+                scen = (int)(((uint64_t)x.x * (uint64_t)job.n_scen) >> 32);
+            }
+            int ign = -1;
+            if (job.ign_mode == 0) {
+                ign = job.ign_cell;
+            } else if (job.ign_mode == 1) {
+                const int nbn = job.land->n_burnable;
+                if (nbn > 0) {
+                    const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
+                    ign = job.burnable[((uint64_t)x.x * (uint64_t)nbn) >> 32];
+                }
+            } else {
+                ign = job.land->centre_cell;
+            }
+            s_scen = scen;
+            s_ign = ign;
+        }
+        __syncthreads();
+        if (s_tag <= 1u) {   // tags exhausted: refill this slot's plane
+            for (size_t i = tid; i < (size_t)slots.plane_cells; i += BLOCK) plane[i] = kPlaneFill;
+            __syncthreads();
+            if (tid == 0) s_tag = kTagFresh;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const uint32_t tag = s_tag - 1u;
+            s_tag = tag;
+            slots.tags[slot] = tag;
+            const int ign = s_ign;
+            if (ign >= 0 && rec_fuel(cells[ign].info) != 0) {
+                const uint32_t v = tag << kMinuteBits;          // minute 0
+                plane[ign] = v;
+                s_W[0][0] = make_uint2((uint32_t)ign, v);
+                s_nW[0] = 1;
+                s_cnt[kCntIgnitions] = 1;
+                if (job.count) atomicAdd(&job.count[ign], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t tag = s_tag;
+        const uint32_t pendv = (tag << kMinuteBits) | kPendingMinute;
+        RateCtx<R> X;
+        X.coef = s_coef;
+        X.coef64 = s_coef64;
+        X.L = land_consts<R>(job.land);
+        X.L64 = land_consts<double>(job.land);
+        X.rows = (const R*)job.table + (size_t)s_scen * job.n_wp * kRowLen;
+        X.rows64 = job.table64 + (size_t)s_scen * job.n_wp * kRowLen;
+        X.seed = job.seed;
+        X.sigma = (R)job.sigma;
+        X.rounding = job.rounding;
+        X.rep = rep;
+
+        uint32_t c_entries = 0, c_conts = 0, c_evals = 0, c_cand = 0, c_impr = 0, c_ign = 0, c_rounds = 0;
+        int max_list = 0;
+        int wc = 0, cc = 0, pc = 0;   // which buffer of each list pair is current
+
+        for (int p = 0; p < job.n_periods; ++p) {
+            const int32_t s = p * P + 1;   // first minute of period p
+            const int32_t e = (p + 1) * P; // last minute of period p
+
+            // Pending cells ignite at the start of p if their rate now passes;
+            // the new labels join this period's first round list.
+            {
+                const int nP = (int)min((int64_t)s_nP[pc], cap);
+                for (int base = 0; base < nP; base += BLOCK) {
+                    const int i = base + tid;
+                    bool act = i < nP;
+                    uint32_t j = 0;
+                    if (act) {
+                        j = gP[pc][i];
+                        act = load_label(&plane[j]) == pendv;
+                    }
+                    bool ok = false;
+                    if (act) {
+                        const CellRec rj = cells[j];
+                        ++c_evals;
+                        ok = head_rate<R>(X, rj.info, rj.grad, rj.sf, j, (uint32_t)p) > thr;
+                    }
+                    bool improved = false, first = false;
+                    const uint32_t v = (tag << kMinuteBits) | (uint32_t)s;
+                    if (ok) {
+                        const uint32_t old = atomicMin(&plane[j], v);
+                        improved = v < old;
+                        first = improved && ((old >> kMinuteBits) != tag || (old & kMinuteMask) == kPendingMinute);
+                        if (first && job.count) atomicAdd(&job.count[j], 1u);
+                    }
+                    c_impr += improved;
+                    c_ign += first;
+                    append_w(improved, make_uint2(j, v), s_W[wc], LCAP, gW[wc], cap, &s_nW[wc], &s_flag);
+                    append_g(act && !ok, j, gP[pc ^ 1], cap, &s_nP[pc ^ 1], &s_flag);
+                }
+            }
+            // Pass 0 advances the continuations of p-1 from the start of p;
+            // passes 1, 2, ... are label-correcting rounds over the cells that
+            // received a smaller arrival inside p, advanced from that minute.
+            // Every pass appends improved cells to the round list of the next
+            // pass (pass 0 to the current one, whose first round follows).
+            for (int pass = 0;; ++pass) {
+                const bool conts = pass == 0;
+                __syncthreads();
+                const int n = conts ? (int)min((int64_t)s_nC[cc], cap)
+                                    : (int)min((int64_t)s_nW[wc], (int64_t)LCAP + cap);
+                if (s_flag) break;
+                if (!conts && n == 0) break;
+                if (n > max_list) max_list = n;
+                c_rounds += !conts;
+                const int wn = conts ? wc : (wc ^ 1);   // round list receiving improvements
+                for (int base = 0; base < n; base += BLOCK) {
+                    const int i = base + tid;
+                    bool act = i < n;
+                    uint32_t c = 0, lab = 0;
+                    int32_t rem[8], cand[8];
+                    if (act) {
+                        if (conts) {
+                            const Cont ct = gC[cc][i];
+                            c = ct.c;
+                            lab = ct.label;
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) {
+                                rem[2 * h] = (int32_t)(ct.rem[h] & 0xFFFFu);
+                                rem[2 * h + 1] = (int32_t)(ct.rem[h] >> 16);
+                            }
+                            ++c_conts;
+                        } else {
+                            const uint2 ent = i < LCAP ? s_W[wc][i] : gW[wc][i - LCAP];
+                            c = ent.x;
+                            lab = ent.y;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) rem[k] = D[k];
+                            ++c_entries;
+                        }
+                        act = load_label(&plane[c]) == lab;
+                    }
+                    bool keep = false;
+                    if (act) {
+                        const CellRec rec = cells[c];
+                        const int32_t m0 = conts ? s : (int32_t)(lab & kMinuteMask) + 1;
+                        c_evals += advance<R>(X, rec, c, p, m0, e, plane, tag, off, rem, cand);
+                        keep = (rem[0] | rem[1] | rem[2] | rem[3] | rem[4] | rem[5] | rem[6] | rem[7]) != 0;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            cand[k] = kNever;
+                            rem[k] = 0;
+                        }
+                    }
+                    // offer the candidates: atomicMin of real labels, or a
+                    // pending mark where the neighbour's rate is below the threshold
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int32_t t = cand[k];
+                        const bool has = act && t != kNever;
+                        const uint32_t j = (uint32_t)((int64_t)c + off[k]);
+                        bool pend = false;
+                        if (has && use_thr) {
+                            const CellRec rj = cells[j];
+                            ++c_evals;
+                            pend = !(head_rate<R>(X, rj.info, rj.grad, rj.sf, j, (uint32_t)p) > thr);
+                        }
+                        bool improved = false, first = false, newpend = false;
+                        uint32_t v = 0;
+                        if (has) {
+                            ++c_cand;
+                            if (!pend) {
+                                v = (tag << kMinuteBits) | (uint32_t)t;
+                                const uint32_t old = atomicMin(&plane[j], v);
+                                improved = v < old;
+                                first = improved &&
+                                        ((old >> kMinuteBits) != tag || (old & kMinuteMask) == kPendingMinute);
+                                if (first && job.count) atomicAdd(&job.count[j], 1u);
+                            } else {
+                                const uint32_t old = atomicMin(&plane[j], pendv);
+                                newpend = old > pendv;
+                            }
+                        }
+                        c_impr += improved;
+                        c_ign += first;
+                        append_w(improved, make_uint2(j, v), s_W[wn], LCAP, gW[wn], cap, &s_nW[wn], &s_flag);
+                        append_g(newpend, j, gP[pc ^ 1], cap, &s_nP[pc ^ 1], &s_flag);
+                    }
+                    // axes still travelling at the end of p continue in p+1
+                    Cont ct;
+                    ct.c = c;
+                    ct.label = lab;
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) ct.rem[h] = (uint32_t)rem[2 * h] | ((uint32_t)rem[2 * h + 1] << 16);
+                    append_g(keep, ct, gC[cc ^ 1], cap, &s_nC[cc ^ 1], &s_flag);
+                }
+                __syncthreads();
+                if (!conts) {
+                    if (tid == 0) s_nW[wc] = 0;
+                    wc ^= 1;
+                }
+            }
+            // ------------------------------------------------- period end
+            __syncthreads();
+            if (tid == 0) {
+                s_nC[cc] = 0;
+                s_nP[pc] = 0;
+            }
+            cc ^= 1;
+            pc ^= 1;
+            __syncthreads();
+            if (s_flag) break;
+            if (s_nC[cc] == 0 && s_nP[pc] == 0) break;   // the fire is out
+        }
+        if (s_flag && tid == 0) atomicOr(&rc->overflow, 1);
+
+        // per-replication counters and outputs
+        atomicAdd(&s_cnt[kCntIgnitions], (unsigned long long)c_ign);
+        atomicAdd(&s_cnt[kCntEntries], (unsigned long long)c_entries);
+        atomicAdd(&s_cnt[kCntConts], (unsigned long long)c_conts);
+        atomicAdd(&s_cnt[kCntEvals], (unsigned long long)c_evals);
+        atomicAdd(&s_cnt[kCntCandidates], (unsigned long long)c_cand);
+        atomicAdd(&s_cnt[kCntImprovements], (unsigned long long)c_impr);
+        if (tid == 0) s_cnt[kCntRounds] = (unsigned long long)c_rounds;
+        atomicMax(&s_cnt[kCntMaxList], (unsigned long long)max_list);
+        if (job.scar || job.arr_minute || job.arr_period) {
+            __syncthreads();
+            const size_t n = (size_t)job.rows * cols;
+            const size_t o = (size_t)lr * n;
+            for (size_t i = tid; i < n; i += BLOCK) {
+                const uint32_t v = load_label(&plane[i]);
+                const bool on = (v >> kMinuteBits) == tag && (v & kMinuteMask) != kPendingMinute;
+                const int32_t t = on ? (int32_t)(v & kMinuteMask) : -1;
+                if (job.scar) job.scar[o + i] = (uint8_t)on;
+                if (job.arr_minute) job.arr_minute[o + i] = t;
+                if (job.arr_period) job.arr_period[o + i] = !on ? -1 : (t == 0 ? 0 : (t - 1) / P);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (job.burned) job.burned[lr] = (int64_t)s_cnt[kCntIgnitions];
+            if (job.ign_out) job.ign_out[lr] = s_ign;
+            if (job.scen_out) job.scen_out[lr] = s_scen;
+            for (int k = 0; k < kCntMaxList; ++k) atomicAdd(&rc->c[k], s_cnt[k]);
+            atomicMax(&rc->c[kCntMaxList], s_cnt[kCntMaxList]);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+static hipError_t launch_prop_t(int block, int grid, const Job* jobs, int n_jobs, int total, const Slots& sl,
+                                RunCounters* rc, hipStream_t s) {
+    switch (block) {
+        case 64: hipLaunchKernelGGL((propagate_kernel<R, 64>), dim3(grid), dim3(64), 0, s, jobs, n_jobs, total, sl, rc); break;
+        case 128: hipLaunchKernelGGL((propagate_kernel<R, 128>), dim3(grid), dim3(128), 0, s, jobs, n_jobs, total, sl, rc); break;
+        case 256: hipLaunchKernelGGL((propagate_kernel<R, 256>), dim3(grid), dim3(256), 0, s, jobs, n_jobs, total, sl, rc); break;
+        case 512: hipLaunchKernelGGL((propagate_kernel<R, 512>), dim3(grid), dim3(512), 0, s, jobs, n_jobs, total, sl, rc); break;
+        case 1024: hipLaunchKernelGGL((propagate_kernel<R, 1024>), dim3(grid), dim3(1024), 0, s, jobs, n_jobs, total, sl, rc); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate(int precision, int block, int grid, const Job* jobs, int n_jobs, int total,
+                            const Slots& slots, RunCounters* rc, hipStream_t s) {
+    return precision == 1 ? launch_prop_t<float>(block, grid, jobs, n_jobs, total, slots, rc, s)
+                          : launch_prop_t<double>(block, grid, jobs, n_jobs, total, slots, rc, s);
+}
+
+template <typename R>
+static int occ_t(int block) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (block) {
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 64>, 64, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 128>, 128, 0); break;
+        case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 256>, 256, 0); break;
+        case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 512>, 512, 0); break;
+        case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 1024>, 1024, 0); break;
+        default: break;
+    }
+    return (e == hipSuccess) ? nb : 0;
+}
+
+int propagate_blocks_per_cu(int precision, int block) {
+    return precision == 1 ? occ_t<float>(block) : occ_t<double>(block);
+}
+
+}  // namespace c2f

@@ -10,8 +10,12 @@ namespace c2f {
 // slot's arrival plane is never cleared between replications; each
 // replication takes a smaller tag, so every value left by an earlier one
 // compares larger than any label of the current one (i.e. "not burned").
+// Minute kPendingMinute marks a cell whose centre was reached while its own
+// rate was below the ignition threshold (it ignites at the start of the
+// first later period that passes); it compares above every real minute.
 constexpr uint32_t kMinuteBits = 20;
 constexpr uint32_t kMinuteMask = (1u << kMinuteBits) - 1u;
+constexpr uint32_t kPendingMinute = kMinuteMask;
 constexpr int32_t kMaxMinutes = (1 << kMinuteBits) - 2;   // longest run, minutes
 constexpr uint32_t kTagFresh = 4095u;                       // tag of a freshly filled plane
 constexpr uint32_t kPlaneFill = 0xFFFFFFFFu;
@@ -21,6 +25,17 @@ constexpr uint32_t kPlaneFill = 0xFFFFFFFFu;
 constexpr int kRowLen = 36;
 constexpr int kRowBE = 4;
 constexpr int kRowRSZ = 20;
+
+// Static per-cell record, 16 bytes, read with one load:
+//   info: fuel code (bits 0-7) | mask of burnable neighbours (bits 8-15,
+//         bit k = axis k: E, NE, N, NW, W, SW, S, SE)
+//   grad: Horn numerators gx (int16, low half) and gn (int16, high half)
+//   sf:   FBP slope factor exp(3.533 (GS/100)^1.2), 10 from 70 % up (1 if flat)
+struct alignas(16) CellRec {
+    uint32_t info;
+    uint32_t grad;
+    double sf;
+};
 
 // Per-landscape values computed on the device at load time.
 struct LandDev {
@@ -35,8 +50,7 @@ struct LandDev {
 
 // One simulation request as the propagation kernel sees it.
 struct Job {
-    const uint8_t* fuel;
-    const uint32_t* grad;      // (gx int16) | (gn int16) << 16
+    const CellRec* cells;
     const int32_t* burnable;   // row-major burnable cells
     const LandDev* land;
     const void* table;         // [n_scen][n_wp][kRowLen] weather terms, double or float
@@ -57,23 +71,38 @@ struct Job {
     int32_t* scen_out;
 };
 
+// A cell whose fire has not yet reached some neighbours by the end of a
+// period: its label and the metres left on each axis (u16 pairs).
+struct Cont {
+    uint32_t c, label;
+    uint32_t rem[4];
+};
+
+// Global part of a work slot's lists, list_cap entries each:
+//   W[2] round lists (spill beyond the LDS part), uint2 (cell, label)
+//   C[2] continuation lists, Cont
+//   P[2] pending cells, uint32
+constexpr int64_t kSlotListBytesPerEntry = 2 * 8 + 2 * 24 + 2 * 4;
+
 // Work slots: one per resident work group.  Each owns an arrival plane of
-// plane_cells labels, four work lists of list_cap entries and a tag.
+// plane_cells labels, its lists and a tag.
 struct Slots {
     uint32_t* planes;
     int64_t plane_cells;
-    uint2* lists;
+    uint8_t* lists;
     int64_t list_cap;
     uint32_t* tags;
 };
 
 enum Counter {
-    kCntEntries = 0,
-    kCntEvals,
-    kCntCandidates,
-    kCntImprovements,
-    kCntIgnitions,
-    kCntMaxList,
+    kCntEntries = 0,     // round-list entries read
+    kCntEvals,           // per (cell, period) rate evaluations
+    kCntCandidates,      // arrival candidates offered
+    kCntImprovements,    // candidates that lowered a label
+    kCntIgnitions,       // cells ignited
+    kCntRounds,          // label-correcting rounds
+    kCntConts,           // continuation entries read
+    kCntMaxList,         // largest list length seen
     kNumCounters = 8
 };
 
@@ -85,8 +114,7 @@ struct RunCounters {
 };
 
 struct EvalArgs {
-    const uint8_t* fuel;
-    const uint32_t* grad;
+    const CellRec* cells;
     const LandDev* land;
     const void* table;
     const double* table64;
