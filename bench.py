@@ -172,8 +172,8 @@ def main():
                    "list_capacity": st["list_capacity"]},
         "burn_maps_per_s": w.reps / (ms / 1e3),
         "burned_cells": burned,
-        "counters": {k: st[k] for k in ("ignitions", "entries", "rate_evals", "candidates",
-                                        "improvements", "relaunches")},
+        "counters": {k: st[k] for k in ("ignitions", "entries", "continuations", "rounds",
+                                        "rate_evals", "candidates", "improvements", "relaunches")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "c2f::propagate_kernel", "kernel_ms": kernel_ms,

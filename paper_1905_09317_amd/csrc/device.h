@@ -34,6 +34,17 @@ __device__ __forceinline__ float m_atan2(float y, float x) { return atan2f(y, x)
 __device__ __forceinline__ double m_fmod(double x, double y) { return fmod(x, y); }
 __device__ __forceinline__ float m_fmod(float x, float y) { return fmodf(x, y); }
 
+// Reciprocals: v_rcp_f32 (1 ulp) for FP32; v_rcp_f64 refined by two Newton
+// steps for FP64 (about 1 ulp).  a * recip(b) replaces the long
+// correctly-rounded division sequences on the rate path.
+__device__ __forceinline__ float recip(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double recip(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    r = fma(fma(-b, r, 1.0), r, r);
+    return r;
+}
+
 template <typename R> struct Const;
 template <> struct Const<double> { static constexpr double pi = 3.14159265358979323846; };
 template <> struct Const<float> { static constexpr float pi = 3.14159265358979323846f; };
@@ -71,7 +82,7 @@ __device__ __forceinline__ R unit24(uint32_t x) {
 // Per (scenario, period) quantities that do not depend on the cell; kept in
 // a table computed once per weather upload.  Layout of one row:
 //   [0] f(F)   [1] ISZ = 0.208 f(F)   [2] WS sin(WAZ)   [3] WS cos(WAZ)
-//   [4 + f] BUI effect of fuel f      [20 + f] zero-wind rate RSZ of pure fuel f
+//   [4 + f] BUI effect of fuel f      [20 + f] 1 - exp(-b_f ISZ) of pure fuel f
 
 template <typename R>
 struct CoefR {
@@ -104,11 +115,16 @@ __device__ void weather_row(const CoefR<R>* coef, float ffmc_f, float bui_f, flo
         if (f != kNonFuel && bui > (R)0)
             be = m_exp((R)50 * m_log(k.q) * ((R)1 / bui - (R)1 / k.bui0));
         row[kRowBE + f] = be;
-        row[kRowRSZ + f] = (k.a > (R)0) ? rsi_pure(k, isz) : (R)0;
+        row[kRowG + f] = (k.a > (R)0) ? -m_expm1(-k.b * isz) : (R)0;
     }
 }
 
 // ----------------------------------------------------------- cell rates
+__device__ __forceinline__ int rec_fuel(uint32_t info) { return (int)(info & 0xFFu); }
+__device__ __forceinline__ uint32_t rec_nbmask(uint32_t info) { return (info >> 8) & 0xFFu; }
+__device__ __forceinline__ int rec_gx(uint32_t g) { return (int)(int16_t)(g & 0xFFFFu); }
+__device__ __forceinline__ int rec_gn(uint32_t g) { return (int)(int16_t)(g >> 16); }
+
 // Landscape-wide constants of the mixed and grass fuels.
 template <typename R>
 struct LandR {
@@ -119,41 +135,47 @@ struct LandR {
 
 template <typename R>
 __device__ __forceinline__ R rsi_fuel(const CoefR<R>* coef, int f, R isi, const LandR<R>& L) {
-    if (f == kM1 || f == kM2) {
-        const R c2 = rsi_pure(coef[kC2], isi);
+    // Mixedwood blends the C-2 and D-1 curves (M-2 takes 0.2 of D-1); every
+    // lane evaluates its own (or the C-2) curve, and the D-1 curve only runs
+    // when some lane of the wave is mixedwood.
+    const bool mixed = (f == kM1 || f == kM2);
+    R r = rsi_pure(coef[mixed ? (int)kC2 : f], isi);
+    if (__any(mixed)) {
         const R d1 = rsi_pure(coef[kD1], isi);
-        const R wd1 = (f == kM2) ? (R)0.2 * ((R)1 - L.pc_w) : ((R)1 - L.pc_w);
-        return L.pc_w * c2 + wd1 * d1;
+        if (mixed) {
+            const R wd1 = (f == kM2) ? (R)0.2 * ((R)1 - L.pc_w) : ((R)1 - L.pc_w);
+            r = L.pc_w * r + wd1 * d1;
+        }
     }
-    const R r = rsi_pure(coef[f], isi);
     return (f >= kO1a) ? r * L.cf : r;
 }
 
-// Spread index that gives rate rsf on the curve of fuel k (scaled by cfac),
-// with the curve's 0.01 floor inside the logarithm.
-template <typename R>
-__device__ __forceinline__ R isf_pure(const CoefR<R>& k, R rsf, R cfac) {
-    R t = (R)1 - m_pow(rsf / (cfac * k.a), (R)1 / k.c);
-    if (t < (R)0.01) t = (R)0.01;
-    return m_log(t) / -k.b;
+// Slope-equivalent wind speed (km/h).  The slope-adjusted zero-wind rate
+// RSF = SF x RSZ inverted on the fuel's rate curve gives ISF = ln(1 - (RSF /
+// (CF a))^(1/c)) / -b with the curve's 0.01 floor inside the logarithm.
+// Because RSZ = CF a (1 - exp(-b ISZ))^c, (RSF / (CF a))^(1/c) is exactly
+// SF^(1/c) (1 - exp(-b ISZ)): sfc/sfd carry SF^(1/c) per cell and the row
+// carries 1 - exp(-b ISZ) per fuel.  Mixedwood takes the percent-conifer
+// weighted ISF of the C-2 and D-1 curves.
+__device__ __forceinline__ double isf_curve(const CoefR<double>& k, double sfc, double g) {
+    double t = 1.0 - sfc * g;
+    if (t < 0.01) t = 0.01;
+    return -log(t) * recip(k.b);
 }
 
-// Slope-equivalent wind speed (km/h) for slope factor sf.
-__device__ __noinline__ double slope_wind(const CoefR<double>* coef, int f, double sf, const double* row,
-                                          const LandR<double>& L) {
+__device__ __noinline__ double slope_wind(const CoefR<double>* coef, int f, double sfc, double sfd,
+                                          const double* row, const LandR<double>& L) {
     const double ff = row[0], isz = row[1];
     double isf;
     if (f == kM1 || f == kM2) {
-        isf = L.pc_w * isf_pure(coef[kC2], sf * row[kRowRSZ + kC2], 1.0) +
-              (1.0 - L.pc_w) * isf_pure(coef[kD1], sf * row[kRowRSZ + kD1], 1.0);
-    } else if (f >= kO1a) {
-        isf = isf_pure(coef[f], sf * row[kRowRSZ + f] * L.cf, L.cf);
+        isf = L.pc_w * isf_curve(coef[kC2], sfc, row[kRowG + kC2]) +
+              (1.0 - L.pc_w) * isf_curve(coef[kD1], sfd, row[kRowG + kD1]);
     } else {
-        isf = isf_pure(coef[f], sf * row[kRowRSZ + f], 1.0);
+        isf = isf_curve(coef[f], sfc, row[kRowG + f]);
     }
-    double wse = log(isf / isz) / 0.05039;
+    double wse = log(isf * recip(isz)) * (1.0 / 0.05039);
     if (wse > 40.0) {
-        wse = (isf < 0.999 * 2.496 * ff) ? 28.0 - log(1.0 - isf / (2.496 * ff)) / 0.0818 : 112.45;
+        wse = (isf < 0.999 * 2.496 * ff) ? 28.0 - log(1.0 - isf * recip(2.496 * ff)) * (1.0 / 0.0818) : 112.45;
     }
     return wse;
 }
@@ -168,18 +190,18 @@ struct CellRates {
 // Everything is evaluated in R except the slope-equivalent wind, which is
 // FP64 in both modes: inverting the rate curve near its asymptote (the
 // WSE > 40 branch) turns a relative error of 1e-7 in ISF into ~1e-4 in WSE.
-// row64 is the FP64 weather row of the same (scenario, period); sf is the
-// cell's slope factor (a static property of the cell).
+// row64 is the FP64 weather row of the same (scenario, period).
 template <typename R>
-__device__ __noinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64, int f, int gx,
-                                   int gn, double sf, const R* row, const double* row64, const LandR<R>& L,
-                                   const LandR<double>& L64) {
+__device__ __noinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64,
+                                                const CellRec& rec, const R* row, const double* row64,
+                                                const LandR<R>& L, const LandR<double>& L64) {
+    const int f = rec_fuel(rec.info), gx = rec_gx(rec.grad), gn = rec_gn(rec.grad);
     R wx = row[2], wy = row[3];
     if ((gx | gn) != 0) {
-        const double g = sqrt((double)gx * (double)gx + (double)gn * (double)gn);
-        const double wse = slope_wind(coef64, f, sf, row64, L64);
-        wx += (R)(wse * ((double)gx / g));                                 // along the upslope unit vector
-        wy += (R)(wse * ((double)gn / g));
+        const double ig = recip(sqrt((double)gx * (double)gx + (double)gn * (double)gn));
+        const double wse = slope_wind(coef64, f, rec.sfc, rec.sfd, row64, L64);
+        wx += (R)(wse * ((double)gx * ig));                                // along the upslope unit vector
+        wy += (R)(wse * ((double)gn * ig));
     }
     const R wsv = m_sqrt(wx * wx + wy * wy);
     const R fw = (wsv <= (R)40) ? m_exp((R)0.05039 * wsv)
@@ -189,8 +211,12 @@ __device__ __noinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const Coef
     CellRates<R> out;
     out.h = rsi_fuel(coef, f, isz * fw, L) * be;
     out.b = rsi_fuel(coef, f, isz * m_exp((R)-0.05039 * wsv), L) * be;
-    if (f >= kO1a) out.lbm1 = (wsv >= (R)1) ? (R)1.1 * m_pow(wsv, (R)0.464) - (R)1 : (R)0;
-    else out.lbm1 = (R)8.729 * m_pow(-m_expm1((R)-0.030 * wsv), (R)2.155);
+    // LB - 1: grass 1.1 WSV^0.464 - 1 (0 below 1 km/h), other fuels
+    // 8.729 (1 - exp(-0.030 WSV))^2.155, as one power per lane
+    const bool grass = f >= kO1a;
+    const R lbase = grass ? wsv : -m_expm1((R)-0.030 * wsv);
+    const R lpow = m_pow(lbase, grass ? (R)0.464 : (R)2.155);
+    out.lbm1 = grass ? ((wsv >= (R)1) ? (R)1.1 * lpow - (R)1 : (R)0) : (R)8.729 * lpow;
     out.lb = (R)1 + out.lbm1;
     out.wx = wx;
     out.wy = wy;
@@ -206,10 +232,6 @@ __device__ __forceinline__ double slope_factor(int gx, int gn, double cell_m) {
     return (gs >= 70.0) ? 10.0 : exp(3.533 * pow(gs / 100.0, 1.2));
 }
 
-__device__ __forceinline__ int rec_fuel(uint32_t info) { return (int)(info & 0xFFu); }
-__device__ __forceinline__ uint32_t rec_nbmask(uint32_t info) { return (info >> 8) & 0xFFu; }
-__device__ __forceinline__ int rec_gx(uint32_t g) { return (int)(int16_t)(g & 0xFFFFu); }
-__device__ __forceinline__ int rec_gn(uint32_t g) { return (int)(int16_t)(g >> 16); }
 
 // Lognormal rate multiplier with mean 1 for (cell, period, rep).
 template <typename R>
@@ -235,12 +257,12 @@ __device__ __forceinline__ R noise_mult(uint64_t seed, uint32_t cell, uint32_t p
 template <typename R>
 __device__ __forceinline__ void axis_rates(const CellRates<R>& cr, R mu, R* x8) {
     const R a = (R)0.5 * (cr.h + cr.b);
-    const R il = (R)1 / cr.lb;
+    const R il = recip(cr.lb);
     const R il2 = il * il;
     const R base = a * il2;                           // a (1 - e^2)
     const R e = m_sqrt(cr.lbm1 * (cr.lbm1 + (R)2)) * il;   // sqrt(1 - 1/LB^2)
-    const R one_m_e = il2 / ((R)1 + e);
-    const R inv_wsv = (cr.wsv > (R)0) ? (R)1 / cr.wsv : (R)0;
+    const R one_m_e = il2 * recip((R)1 + e);
+    const R inv_wsv = (cr.wsv > (R)0) ? recip(cr.wsv) : (R)0;
     const R cx = cr.wx * inv_wsv, cy = cr.wy * inv_wsv;   // unit head direction
     const R s = (R)0.70710678118654752440;
     const R ux[8] = {(R)1, s, (R)0, -s, (R)-1, -s, (R)0, s};
@@ -251,9 +273,40 @@ __device__ __forceinline__ void axis_rates(const CellRates<R>& cr, R mu, R* x8) 
         R r = base;
         if (c > (R)0) {
             const R dx = cx - ux[k], dy = cy - uy[k];
-            r = base / (one_m_e + e * ((R)0.5 * (dx * dx + dy * dy)));
+            r = base * recip(one_m_e + e * ((R)0.5 * (dx * dx + dy * dy)));
         }
         x8[k] = mu * r;
+    }
+}
+
+// The same rates floored to integer m/min after adding u_k: 1/2, or the
+// 24-bit uniforms of the words ua (axes 0-3) and ub (axes 4-7).
+template <typename R>
+__device__ __forceinline__ void axis_rates_q(const CellRates<R>& cr, R mu, bool stochastic, uint4 ua, uint4 ub,
+                                             int32_t* q) {
+    const R a = (R)0.5 * (cr.h + cr.b);
+    const R il = recip(cr.lb);
+    const R il2 = il * il;
+    const R base = a * il2;
+    const R e = m_sqrt(cr.lbm1 * (cr.lbm1 + (R)2)) * il;
+    const R one_m_e = il2 * recip((R)1 + e);
+    const R inv_wsv = (cr.wsv > (R)0) ? recip(cr.wsv) : (R)0;
+    const R cx = cr.wx * inv_wsv, cy = cr.wy * inv_wsv;
+    const R s = (R)0.70710678118654752440;
+    const R ux[8] = {(R)1, s, (R)0, -s, (R)-1, -s, (R)0, s};
+    const R uy[8] = {(R)0, s, (R)1, s, (R)0, -s, (R)-1, -s};
+    const uint32_t w[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const R c = ux[k] * cx + uy[k] * cy;
+        R r = base;
+        if (c > (R)0) {
+            const R dx = cx - ux[k], dy = cy - uy[k];
+            r = base * recip(one_m_e + e * ((R)0.5 * (dx * dx + dy * dy)));
+        }
+        const R u = stochastic ? unit24<R>(w[k]) : (R)0.5;
+        const R v = m_floor(mu * r + u);
+        q[k] = (v < (R)1073741824) ? (int32_t)v : 1073741824;
     }
 }
 
@@ -296,38 +349,24 @@ struct RateCtx {
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
 // the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.
 template <typename R>
-__device__ __forceinline__ void axis_q(const RateCtx<R>& X, uint32_t info, uint32_t grad, double sf,
-                                       uint32_t cell, uint32_t period, int32_t* q) {
+__device__ __forceinline__ void axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
+                                       int32_t* q) {
     const size_t ro = (size_t)period * kRowLen;
-    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec_fuel(info), rec_gx(grad), rec_gn(grad), sf,
-                                          X.rows + ro, X.rows64 + ro, X.L, X.L64);
+    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
     const R mu = noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
-    R x[8];
-    axis_rates<R>(cr, mu, x);
-    R u[8];
-    if (X.rounding == 0) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) u[k] = (R)0.5;
-    } else {
-        const uint4 a = draw(X.seed, cell, period, X.rep, 1u);
-        const uint4 b = draw(X.seed, cell, period, X.rep, 2u);
-        u[0] = unit24<R>(a.x); u[1] = unit24<R>(a.y); u[2] = unit24<R>(a.z); u[3] = unit24<R>(a.w);
-        u[4] = unit24<R>(b.x); u[5] = unit24<R>(b.y); u[6] = unit24<R>(b.z); u[7] = unit24<R>(b.w);
+    uint4 ua = make_uint4(0u, 0u, 0u, 0u), ub = ua;
+    if (X.rounding != 0) {
+        ua = draw(X.seed, cell, period, X.rep, 1u);
+        ub = draw(X.seed, cell, period, X.rep, 2u);
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const R v = m_floor(x[k] + u[k]);
-        q[k] = (v < (R)1073741824) ? (int32_t)v : 1073741824;
-    }
+    axis_rates_q<R>(cr, mu, X.rounding != 0, ua, ub, q);
 }
 
 // Head rate times the noise multiplier: the receiving cell's ignition test.
 template <typename R>
-__device__ __forceinline__ R head_rate(const RateCtx<R>& X, uint32_t info, uint32_t grad, double sf,
-                                       uint32_t cell, uint32_t period) {
+__device__ __forceinline__ R head_rate(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period) {
     const size_t ro = (size_t)period * kRowLen;
-    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec_fuel(info), rec_gx(grad), rec_gn(grad), sf,
-                                          X.rows + ro, X.rows64 + ro, X.L, X.L64);
+    const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
     return cr.h * noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
 }
 

@@ -66,9 +66,19 @@ __global__ void cellrec_kernel(const uint8_t* __restrict__ fuel, const int16_t* 
             }
         }
         CellRec rec;
-        rec.info = (uint32_t)fuel[i] | (mask << 8);
+        const int f = fuel[i];
+        rec.info = (uint32_t)f | (mask << 8);
         rec.grad = (uint32_t)(uint16_t)(int16_t)gx | ((uint32_t)(uint16_t)(int16_t)gn << 16);
-        rec.sf = slope_factor(gx, gn, cell_m);
+        rec.pad[0] = rec.pad[1] = 0u;
+        rec.sfc = 1.0;
+        rec.sfd = 1.0;
+        if ((gx | gn) != 0 && f != kNonFuel) {
+            // SF^(1/c) of the rate curve(s) the cell's slope effect uses
+            const double sf = slope_factor(gx, gn, cell_m);
+            const bool mixed = (f == kM1 || f == kM2);
+            rec.sfc = pow(sf, 1.0 / kCoef64[mixed ? kC2 : f].c);
+            if (mixed) rec.sfd = pow(sf, 1.0 / kCoef64[kD1].c);
+        }
         recs[i] = rec;
     }
 }
@@ -258,13 +268,12 @@ __global__ void eval_ros_kernel(EvalArgs a) {
             }
             continue;
         }
-        const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, f, rec_gx(rec.grad), rec_gn(rec.grad), rec.sf,
-                                              X.rows + ro, X.rows64 + ro, X.L, X.L64);
+        const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
         const R mu = noise_mult<R>(a.seed, (uint32_t)i, (uint32_t)a.period, a.rep, (R)a.sigma);
         R x[8];
         axis_rates<R>(cr, mu, x);
         int32_t q[8];
-        axis_q<R>(X, rec.info, rec.grad, rec.sf, (uint32_t)i, (uint32_t)a.period, q);
+        axis_q<R>(X, rec, (uint32_t)i, (uint32_t)a.period, q);
         if (a.hros) a.hros[i] = (double)(cr.h * mu);
         if (a.bros) a.bros[i] = (double)(cr.b * mu);
         if (a.fros) a.fros[i] = (double)((cr.h + cr.b) / ((R)2 * cr.lb) * mu);

@@ -78,42 +78,53 @@ __device__ __forceinline__ void append_g(bool pred, const T& val, T* glob, int64
     }
 }
 
-// Advance cell c (label lab) through period p from minute m0 to e.  rem[k]
-// holds the metres left on axis k (0 = done).  On return cand[k] is the
+// Exclusive prefix sum of `v` over the lanes of a wave, and the wave total.
+__device__ __forceinline__ int wave_excl_scan(int v, int& total) {
+    const int lane = __lane_id();
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    total = __shfl(x, 63);
+    return x - v;
+}
+
+// Advance cell c (label lab) through period p from minute m0 to e.  nbv[k]
+// is the label of neighbour k read at the start of the pass; rem[k] holds
+// the metres left on axis k (0 = done).  On return cand[k] is the
 // minute the fire reaches neighbour k inside p (or kNever) and rem[] the
 // metres left at the end of p for axes still worth following.  An axis is
 // dropped once its neighbour already holds a label no later candidate can
 // beat, or is pending (its ignition minute is then already determined).
 template <typename R>
 __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, uint32_t c, int p, int32_t m0,
-                                       int32_t e, const uint32_t* __restrict__ plane, uint32_t tag,
-                                       const int32_t* off, int32_t* rem, int32_t* cand) {
+                                       int32_t e, const uint32_t* nbv, uint32_t tag, int32_t* rem, int32_t* cand) {
     const uint32_t nb = rec_nbmask(rec.info);
-    int32_t curv[8];
-    uint32_t live = 0;
+    uint32_t live = 0, settled = 0;   // settled: neighbour label <= e + 1
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         cand[k] = kNever;
-        curv[k] = kNever;
         if (!((nb >> k) & 1u) || rem[k] <= 0) {
             rem[k] = 0;
             continue;
         }
-        const uint32_t v = plane[(int64_t)c + off[k]];
+        const uint32_t v = nbv[k];
         if ((v >> kMinuteBits) == tag) {
             const int32_t t = (int32_t)(v & kMinuteMask);
             if (t == (int32_t)kPendingMinute || t <= m0) {
                 rem[k] = 0;
                 continue;
             }
-            curv[k] = t;
+            if (t <= e + 1) settled |= 1u << k;
         }
         live |= 1u << k;
     }
     int evals = 0;
     if (live != 0u && m0 <= e) {
         int32_t q[8];
-        axis_q<R>(X, rec.info, rec.grad, rec.sf, c, (uint32_t)p, q);
+        axis_q<R>(X, rec, c, (uint32_t)p, q);
         evals = 1;
         const int64_t n = (int64_t)(e - m0 + 1);
 #pragma unroll
@@ -125,7 +136,7 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
                 rem[k] = 0;
             } else {
                 rem[k] -= (int32_t)((int64_t)qk * n);
-                if (curv[k] <= e + 1) rem[k] = 0;   // nothing after p can beat it
+                if ((settled >> k) & 1u) rem[k] = 0;   // nothing after p can beat it
             }
         }
     }
@@ -182,6 +193,7 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
         const int lr = item - job.item_base;
         const uint32_t rep = (uint32_t)(job.rep_offset + lr);
         const int cols = job.cols;
+        const int rows = job.rows;
         const int P = job.period_min;
         const CellRec* __restrict__ cells = job.cells;
         const bool use_thr = job.threshold > 0.0f;
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
                     if (act) {
                         const CellRec rj = cells[j];
                         ++c_evals;
-                        ok = head_rate<R>(X, rj.info, rj.grad, rj.sf, j, (uint32_t)p) > thr;
+                        ok = head_rate<R>(X, rj, j, (uint32_t)p) > thr;
                     }
                     bool improved = false, first = false;
                     const uint32_t v = (tag << kMinuteBits) | (uint32_t)s;
@@ -312,6 +324,9 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
                     bool act = i < n;
                     uint32_t c = 0, lab = 0;
                     int32_t rem[8], cand[8];
+                    uint32_t nbv[8];
+                    CellRec rec;
+                    rec.info = 0;
                     if (act) {
                         if (conts) {
                             const Cont ct = gC[cc][i];
@@ -331,13 +346,26 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
                             for (int k = 0; k < 8; ++k) rem[k] = D[k];
                             ++c_entries;
                         }
-                        act = load_label(&plane[c]) == lab;
+                        // issue every load of the entry at once: own label,
+                        // cell record and the labels of the in-grid neighbours
+                        const uint32_t own = load_label(&plane[c]);
+                        rec = cells[c];
+                        const int r = (int)(c / (uint32_t)cols), col = (int)(c - (uint32_t)r * (uint32_t)cols);
+                        // axes E NE N NW W SW S SE = bits 0..7; drop those leaving the grid
+                        uint32_t inb = 0xFFu;
+                        if (col + 1 >= cols) inb &= ~0x83u;   // E, NE, SE
+                        if (col == 0) inb &= ~0x38u;          // NW, W, SW
+                        if (r == 0) inb &= ~0x0Eu;            // NE, N, NW
+                        if (r + 1 >= rows) inb &= ~0xE0u;     // SW, S, SE
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            nbv[k] = ((inb >> k) & 1u) ? plane[(int64_t)c + off[k]] : kPlaneFill;
+                        act = own == lab;
                     }
                     bool keep = false;
                     if (act) {
-                        const CellRec rec = cells[c];
                         const int32_t m0 = conts ? s : (int32_t)(lab & kMinuteMask) + 1;
-                        c_evals += advance<R>(X, rec, c, p, m0, e, plane, tag, off, rem, cand);
+                        c_evals += advance<R>(X, rec, c, p, m0, e, nbv, tag, rem, cand);
                         keep = (rem[0] | rem[1] | rem[2] | rem[3] | rem[4] | rem[5] | rem[6] | rem[7]) != 0;
                     } else {
 #pragma unroll
@@ -347,38 +375,76 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
                         }
                     }
                     // offer the candidates: atomicMin of real labels, or a
-                    // pending mark where the neighbour's rate is below the threshold
+                    // pending mark where the neighbour's rate is below the
+                    // threshold.  All atomics are issued before any result is
+                    // used so that their latencies overlap.
+                    uint32_t hasm = 0, pendm = 0, impr = 0;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int32_t t = cand[k];
-                        const bool has = act && t != kNever;
-                        const uint32_t j = (uint32_t)((int64_t)c + off[k]);
-                        bool pend = false;
-                        if (has && use_thr) {
+                    for (int k = 0; k < 8; ++k) hasm |= (act && cand[k] != kNever) ? (1u << k) : 0u;
+                    if (use_thr) {
+                        for (uint32_t m = hasm; m != 0u; m &= m - 1u) {
+                            const int k = __ffs(m) - 1;
+                            const uint32_t j = (uint32_t)((int64_t)c + off[k]);
                             const CellRec rj = cells[j];
                             ++c_evals;
-                            pend = !(head_rate<R>(X, rj.info, rj.grad, rj.sf, j, (uint32_t)p) > thr);
+                            if (!(head_rate<R>(X, rj, j, (uint32_t)p) > thr)) pendm |= 1u << k;
                         }
-                        bool improved = false, first = false, newpend = false;
-                        uint32_t v = 0;
-                        if (has) {
-                            ++c_cand;
-                            if (!pend) {
-                                v = (tag << kMinuteBits) | (uint32_t)t;
-                                const uint32_t old = atomicMin(&plane[j], v);
-                                improved = v < old;
-                                first = improved &&
-                                        ((old >> kMinuteBits) != tag || (old & kMinuteMask) == kPendingMinute);
-                                if (first && job.count) atomicAdd(&job.count[j], 1u);
-                            } else {
-                                const uint32_t old = atomicMin(&plane[j], pendv);
-                                newpend = old > pendv;
+                    }
+                    uint32_t old[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        old[k] = 0u;
+                        if ((hasm >> k) & 1u) {
+                            const uint32_t v = ((pendm >> k) & 1u) ? pendv
+                                                                   : (tag << kMinuteBits) | (uint32_t)cand[k];
+                            old[k] = atomicMin(&plane[(int64_t)c + off[k]], v);
+                        }
+                    }
+                    uint32_t newpend = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if (!((hasm >> k) & 1u)) continue;
+                        if ((pendm >> k) & 1u) {
+                            if (old[k] > pendv) newpend |= 1u << k;
+                            continue;
+                        }
+                        const uint32_t v = (tag << kMinuteBits) | (uint32_t)cand[k];
+                        if (v < old[k]) {
+                            impr |= 1u << k;
+                            if ((old[k] >> kMinuteBits) != tag || (old[k] & kMinuteMask) == kPendingMinute) {
+                                ++c_ign;
+                                if (job.count) atomicAdd(&job.count[(int64_t)c + off[k]], 1u);
                             }
                         }
-                        c_impr += improved;
-                        c_ign += first;
-                        append_w(improved, make_uint2(j, v), s_W[wn], LCAP, gW[wn], cap, &s_nW[wn], &s_flag);
-                        append_g(newpend, j, gP[pc ^ 1], cap, &s_nP[pc ^ 1], &s_flag);
+                    }
+                    c_cand += __popc(hasm);
+                    // append this lane's improved neighbours with one wave scan
+                    const int ni = __popc(impr);
+                    c_impr += ni;
+                    int wtot;
+                    const int pre = wave_excl_scan(ni, wtot);
+                    if (wtot > 0) {
+                        const int leader = 0;
+                        int wbase = 0;
+                        if (__lane_id() == leader) wbase = atomicAdd(&s_nW[wn], wtot);
+                        wbase = __shfl(wbase, leader);
+                        int idx = wbase + pre;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            if (!((impr >> k) & 1u)) continue;
+                            const uint2 val = make_uint2((uint32_t)((int64_t)c + off[k]),
+                                                         (tag << kMinuteBits) | (uint32_t)cand[k]);
+                            if (idx < LCAP) s_W[wn][idx] = val;
+                            else if ((int64_t)(idx - LCAP) < cap) gW[wn][idx - LCAP] = val;
+                            else s_flag = 1;
+                            ++idx;
+                        }
+                    }
+                    if (use_thr) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+                            append_g(((newpend >> k) & 1u) != 0u, (uint32_t)((int64_t)c + off[k]), gP[pc ^ 1], cap,
+                                     &s_nP[pc ^ 1], &s_flag);
                     }
                     // axes still travelling at the end of p continue in p+1
                     Cont ct;

@@ -21,20 +21,28 @@ constexpr uint32_t kTagFresh = 4095u;                       // tag of a freshly 
 constexpr uint32_t kPlaneFill = 0xFFFFFFFFu;
 
 // Weather-table row: [0] f(F), [1] ISZ, [2] WS sin(WAZ), [3] WS cos(WAZ),
-// [4 + f] BUI effect of fuel f, [20 + f] zero-wind rate of pure fuel f.
+// [4 + f] BUI effect of fuel f, [20 + f] 1 - exp(-b_f ISZ) of pure fuel f
+// (the zero-wind rate RSZ = a (1 - exp(-b ISZ))^c without its a and c).
 constexpr int kRowLen = 36;
 constexpr int kRowBE = 4;
-constexpr int kRowRSZ = 20;
+constexpr int kRowG = 20;
 
-// Static per-cell record, 16 bytes, read with one load:
+// Static per-cell record, 32 bytes:
 //   info: fuel code (bits 0-7) | mask of burnable neighbours (bits 8-15,
 //         bit k = axis k: E, NE, N, NW, W, SW, S, SE)
 //   grad: Horn numerators gx (int16, low half) and gn (int16, high half)
-//   sf:   FBP slope factor exp(3.533 (GS/100)^1.2), 10 from 70 % up (1 if flat)
+//   sfc:  SF^(1/c) for the cell's own rate curve (the C-2 curve for M-1/M-2),
+//         with SF the FBP slope factor exp(3.533 (GS/100)^1.2), 10 from
+//         70 % up; 1 on flat ground
+//   sfd:  SF^(1/c) for the D-1 curve (M-1/M-2 cells only)
+// With these, the slope-adjusted spread index of a fuel with curve
+// a (1 - exp(-b ISI))^c is ISF = ln(1 - sfc (1 - exp(-b ISZ))) / -b.
 struct alignas(16) CellRec {
     uint32_t info;
     uint32_t grad;
-    double sf;
+    uint32_t pad[2];
+    double sfc;
+    double sfd;
 };
 
 // Per-landscape values computed on the device at load time.
