@@ -57,32 +57,146 @@ def dense_outputs(w) -> tuple:
     return ("burn_count", "burned_cells")
 
 
-def cpu_baseline(w, budget_s: float) -> dict:
+def _oracle_kwargs(w) -> dict:
+    import numpy as np
+    return dict(cell_m=w.cell_m, n_periods=w.n_periods, seed=w.seed,
+                sigma=np.float32(w.sigma).item(), threshold=w.threshold, rounding=w.rounding,
+                ignition_mode=w.ignition_mode, ignition_cell=w.ignition_cell,
+                scenario_mode=w.scenario_mode, scenario=w.scenario, period_min=w.period_min)
+
+
+def _oracle_shard(arg) -> tuple:
+    """One CPU worker: simulate replications first, first + stride, ... one at
+    a time with the oracle until the time budget is spent."""
+    folder, kw, first, stride, reps, budget_s = arg
     import numpy as np
 
     import oracle
-    reps_done = 0
+    fuel = np.load(os.path.join(folder, "fuel.npy"), mmap_mode="r")
+    elev = np.load(os.path.join(folder, "elev.npy"), mmap_mode="r")
+    weather = np.load(os.path.join(folder, "weather.npy"))
+    fuel, elev = np.ascontiguousarray(fuel), np.ascontiguousarray(elev)
     t0 = time.perf_counter()
-    n_runs = 0
-    chunk = 1 if w.reps == 1 else max(1, min(w.reps, 4))
+    done, r = 0, first
     while True:
-        off = reps_done % w.reps if w.reps > 1 else 0
-        n = min(chunk, w.reps - off) if w.reps > 1 else 1
-        oracle.simulate(w.fuel, w.elev, w.weather, cell_m=w.cell_m, n_periods=w.n_periods, reps=n,
-                        rep_offset=off, seed=w.seed, sigma=np.float32(w.sigma).item(),
-                        threshold=w.threshold, rounding=w.rounding, ignition_mode=w.ignition_mode,
-                        ignition_cell=w.ignition_cell, scenario_mode=w.scenario_mode,
-                        scenario=w.scenario, period_min=w.period_min, want_rep_outputs=(w.reps == 1))
-        reps_done += n
-        n_runs += 1
+        oracle.simulate(fuel, elev, weather, reps=1, rep_offset=r % reps, want_rep_outputs=False,
+                        **kw)
+        done += 1
+        r += stride
         if time.perf_counter() - t0 >= budget_s:
             break
-    dt = time.perf_counter() - t0
-    cu = reps_done * w.rows * w.cols * w.n_periods
-    what = (f"the full workload simulated {n_runs} times" if w.reps == 1
-            else f"{reps_done} of the {w.reps} replications")
-    return {"value": cu / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what} by the single-threaded FP64 oracle in {dt:.1f} s"}
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s: float, procs: int) -> dict:
+    """The FP64 oracle on this host: a single fire repeated on one core, or
+    the replications sharded over `procs` worker processes."""
+    import multiprocessing
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+    kw = _oracle_kwargs(w)
+    if w.reps == 1 or procs <= 1:
+        t0 = time.perf_counter()
+        runs = 0
+        while True:
+            oracle.simulate(w.fuel, w.elev, w.weather, reps=1, rep_offset=runs % w.reps,
+                            want_rep_outputs=(w.reps == 1), **kw)
+            runs += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        what = (f"the full workload simulated {runs} times" if w.reps == 1
+                else f"{runs} of the {w.reps} replications")
+        return {"value": runs * w.rows * w.cols * w.n_periods / dt, "unit": "cell-updates/s",
+                "cores": 1, "kind": "oracle",
+                "sample": f"{what} by the single-threaded FP64 oracle in {dt:.1f} s"}
+    with tempfile.TemporaryDirectory() as folder:
+        np.save(os.path.join(folder, "fuel.npy"), w.fuel)
+        np.save(os.path.join(folder, "elev.npy"),
+                w.elev if w.elev is not None else np.zeros_like(w.fuel, dtype=np.int16))
+        np.save(os.path.join(folder, "weather.npy"), w.weather)
+        args = [(folder, kw, k, procs, w.reps, budget_s) for k in range(procs)]
+        # spawned workers: fresh interpreters that never touch the GPU
+        with multiprocessing.get_context("spawn").Pool(procs) as pool:
+            res = pool.map(_oracle_shard, args)
+    reps_done = sum(r[0] for r in res)
+    dt = max(r[1] for r in res)
+    return {"value": reps_done * w.rows * w.cols * w.n_periods / dt, "unit": "cell-updates/s",
+            "cores": procs, "kind": "oracle",
+            "sample": (f"{reps_done} of the {w.reps} replications, sharded over {procs} "
+                       f"single-threaded FP64 oracle processes, in {dt:.1f} s")}
+
+
+def copy_calibration(args) -> None:
+    """Plain copy of known size: each launch reads and writes args.copy_mib MiB."""
+    import torch
+    n = args.copy_mib << 20
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "steps": args.steps,
+                      "ms_per_copy": ms, "GB_per_s": 2 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
+def served_bench(args) -> None:
+    """Continuous-batching service: a Poisson stream of Monte-Carlo queries
+    (side log-uniform 128..4096 cells, 1..256 reps, 48 h, FP64 rates) on
+    landscapes already resident in HBM; latency from submission to delivered
+    burn counts, by the library's clock."""
+    import torch  # noqa: F401  (HIP runtime shared with torch)
+
+    from paper_1905_09317_amd import Simulator, inputs
+    from paper_1905_09317_amd.serve import load_stream, run_stream
+
+    st = inputs.served_stream(n_queries=args.queries, rate_per_s=args.rate)
+    print(f"[bench] {st.name}: {len(st.queries)} queries, loading landscapes", file=sys.stderr,
+          flush=True)
+    sim = Simulator(0)
+    sim.set_serving(lanes=args.lanes)
+    wx, lands = load_stream(sim, st)
+    print("[bench] landscapes resident; warming the lanes", file=sys.stderr, flush=True)
+    warm = sorted(st.queries, key=lambda q: q.side * q.side * q.reps)[:max(0, args.warmup) * 4]
+    if warm:
+        run_stream(sim, st, wx, lands, queries=warm, pace=False)
+    print("[bench] replaying the stream", file=sys.stderr, flush=True)
+    s = run_stream(sim, st, wx, lands)
+    line = {
+        "metric": "cell-updates/s (reps x cells x periods), served stream",
+        "value": s["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": len(warm),
+        "ms_per_step": s["span_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": st.name, "queries": len(st.queries), "rate_per_s": args.rate,
+                   "side": [128, 4096], "reps": [1, 256], "n_periods": st.n_periods,
+                   "lanes": args.lanes, "ros_sigma": st.sigma, "rounding": "stochastic",
+                   "rate_precision": "fp64", "ignition": "uniform-burnable"},
+        "latency_ms": {"p50": s["latency_ms_p50"], "p99": s["latency_ms_p99"],
+                       "mean": s["latency_ms_mean"], "max": s["latency_ms_max"]},
+        "queue_ms": {"p50": s["queue_ms_p50"], "p99": s["queue_ms_p99"]},
+        "served": {k: s[k] for k in ("completed", "failed", "errors", "offered_cell_updates_per_s",
+                                     "arrival_span_s", "drain_ms", "sustained", "batches",
+                                     "mean_batch_requests", "lanes_used")},
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+    sim.close()
 
 
 def main():
@@ -91,11 +205,20 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single",
-                    choices=["single", "single64", "batched", "large", "tiny"])
+                    choices=["single", "single64", "batched", "large", "tiny", "served"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle worker processes for multi-replication workloads "
+                         "(default: min(16, host CPUs))")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--queries", type=int, default=1000, help="served: queries in the stream")
+    ap.add_argument("--rate", type=float, default=50.0, help="served: Poisson arrivals per second")
+    ap.add_argument("--lanes", type=int, default=4, help="served: concurrent serving lanes")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of the simulation, run a plain device-to-device copy of this "
+                         "many MiB per step (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the simulation of one GPU's share "
@@ -105,6 +228,14 @@ def main():
     import torch
 
     from paper_1905_09317_amd import Request, Simulator
+
+    if args.copy_mib:
+        copy_calibration(args)
+        return
+
+    if args.workload == "served":
+        served_bench(args)
+        return
 
     w = make_workload(args.workload)
     print(f"[bench] workload {w.name}: {w.rows}x{w.cols}, reps {w.reps}, periods {w.n_periods}",
@@ -181,7 +312,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, procs)
     print(json.dumps(line), flush=True)
     sim.close()
 

@@ -29,8 +29,9 @@
  *   - Host pointers passed in are only read during the call; the library
  *     copies what it keeps.  All device memory is owned by the context and
  *     released by c2f_destroy().
- *   - One context per host thread for c2f_simulate/c2f_eval_ros; the
- *     serving calls (c2f_submit/poll/wait) may be used from several threads.
+ *   - Entry points may be called from several threads: synchronous calls
+ *     on one context are serialised; served requests run on their own lanes
+ *     beside them.
  *   - Results depend only on (landscape, weather, params including seed):
  *     never on block size, batch composition or co-resident work.
  */
@@ -173,9 +174,10 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
 c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]);
 
 /* Tuning.  block_threads: threads per work group of the propagation kernel
- * (64..1024, multiple of 64; 0 = automatic).  list_capacity: entries per
- * per-replication work list (0 = automatic).  A too small capacity is
- * detected and the run repeated with a larger one, so results never change. */
+ * (64..1024, multiple of 64; 0 = automatic).  list_capacity: least number
+ * of entries per per-replication work list (0 = automatic).  A too small
+ * capacity is detected and the run repeated with a larger one, so results
+ * never change. */
 c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capacity);
 
 /* Pick block size and list capacity for requests like `representative` by
@@ -199,14 +201,55 @@ typedef struct {
 } c2f_run_stats;
 c2f_status c2f_get_stats(const c2f_ctx* ctx, c2f_run_stats* out);
 
-/* Serving: submit a request; it is admitted to the device when its memory
- * fits the context's budget, batched with other admitted requests, and
- * completed asynchronously.  Output pointers must stay valid until done.
- * EBUSY when max_queue requests are already waiting. */
+/* Serving (continuous batching).  c2f_submit validates a request and queues
+ * it; serving lanes (each a HIP stream with its own work slots) take
+ * requests from the head of the queue in arrival order and run them as one
+ * fused launch, so that batches on different lanes overlap on the device.
+ * A request is admitted when the device memory its lane must add (arrival
+ * planes, work lists, output staging) fits within the context's budget
+ * (hbm_budget_bytes of c2f_create, else 90 % of the memory free at
+ * creation) next to what is already held; otherwise it waits for running
+ * batches to finish, and idle lanes release their buffers.  A request that
+ * does not fit even alone runs alone with fewer resident work slots, or
+ * fails with ENOMEM.  Results are identical to c2f_simulate of the same
+ * request.  Output pointers (host or device) must stay valid until the
+ * request completes; device outputs are written on the lane's stream and
+ * are complete when c2f_wait returns.  A landscape or weather set used by a
+ * queued or running request cannot be unloaded (EBUSY).
+ * EBUSY from c2f_submit when max_queue (4096) requests are already waiting. */
 c2f_status c2f_submit(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out,
                       uint64_t* ticket);
+/* *done = 1 once the request has completed (successfully or not). */
 c2f_status c2f_poll(c2f_ctx* ctx, uint64_t ticket, int32_t* done);
+/* Block until the request completes; returns its status and forgets the
+ * ticket (ESTATE for an unknown or already waited ticket). */
 c2f_status c2f_wait(c2f_ctx* ctx, uint64_t ticket);
+
+/* Timing of a completed request, host steady clock in ms since the context
+ * was created: submitted, started on a lane, outputs delivered. */
+typedef struct {
+    double submit_ms, start_ms, done_ms;
+    double kernel_ms;          /* propagation time of the batch it ran in */
+    int32_t batch_requests;    /* requests in that batch */
+    int32_t batch_reps;        /* replications in that batch */
+    int32_t lane;              /* serving lane that ran it */
+    int32_t status;            /* its c2f_status */
+} c2f_ticket_info;
+/* c2f_wait that also reports the request's timing (info may be NULL). */
+c2f_status c2f_wait_info(c2f_ctx* ctx, uint64_t ticket, c2f_ticket_info* info);
+
+/* Serving configuration, before the first c2f_submit (ESTATE after):
+ * lanes (1..16, default 4) concurrent batches; max_batch_reps (default
+ * 65536) replications fused into one batch; max_batch_grid resident work
+ * groups one batch may use (0 = all that fit the device); admit_bytes the
+ * device bytes admission plans against (0 = keep the default; at most the
+ * context's budget). */
+c2f_status c2f_set_serving(c2f_ctx* ctx, int32_t lanes, int32_t max_batch_reps,
+                           int32_t max_batch_grid, uint64_t admit_bytes);
+
+/* Device memory the context holds now (landscapes, weather, work slots,
+ * lists, staging) and the limit serving admission plans against. */
+c2f_status c2f_get_memory(c2f_ctx* ctx, uint64_t* bytes_held, uint64_t* admit_limit);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,13 @@ class RunStats(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
 
 
+class TicketInfo(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("batch_requests", ctypes.c_int32), ("batch_reps", ctypes.c_int32),
+                ("lane", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -84,6 +91,9 @@ def load() -> ctypes.CDLL:
         "c2f_submit": ([P, pp(SimParams), pp(Outputs), pp(u64)], i32),
         "c2f_poll": ([P, u64, pp(i32)], i32),
         "c2f_wait": ([P, u64], i32),
+        "c2f_wait_info": ([P, u64, pp(TicketInfo)], i32),
+        "c2f_set_serving": ([P, i32, i32, i32, u64], i32),
+        "c2f_get_memory": ([P, pp(u64), pp(u64)], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -96,4 +106,5 @@ def load() -> ctypes.CDLL:
 DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2f_load_landscape",
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
             "c2f_simulate_batch", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
-            "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait")
+            "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
+            "c2f_wait_info", "c2f_set_serving", "c2f_get_memory")

@@ -11,7 +11,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _lib
-from ._lib import Outputs, RunStats, SimParams, WeatherRow
+from ._lib import Outputs, RunStats, SimParams, TicketInfo, WeatherRow
 
 OUTPUT_NAMES = ("scar", "arrival_period", "arrival_minute", "burn_count", "burned_cells",
                 "ignition_cell", "scenario")
@@ -217,6 +217,19 @@ class Simulator:
         return {k: getattr(s, k) for k, _ in RunStats._fields_}
 
     # ------------------------------------------------------------ serving
+    def set_serving(self, lanes: int = 4, max_batch_reps: int = 1 << 16, max_batch_grid: int = 0,
+                    admit_bytes: int = 0):
+        """Serving lanes, batch limits and admission memory; call before the
+        first submit."""
+        self._check(self._L.c2f_set_serving(self._ctx, int(lanes), int(max_batch_reps),
+                                            int(max_batch_grid), int(admit_bytes)))
+
+    def memory(self) -> tuple[int, int]:
+        """(device bytes held by the context, serving admission limit)."""
+        held, limit = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.c2f_get_memory(self._ctx, ctypes.byref(held), ctypes.byref(limit)))
+        return held.value, limit.value
+
     def submit(self, req: Request) -> tuple[int, dict]:
         """Queue a request; returns (ticket, outputs that fill in when done)."""
         res, o = self._alloc_outputs(req)
@@ -232,11 +245,16 @@ class Simulator:
         return bool(d.value)
 
     def wait(self, ticket: int) -> dict:
+        return self.wait_info(ticket)[0]
+
+    def wait_info(self, ticket: int) -> tuple[dict, dict]:
+        """Block until the request completes; returns (outputs, timing)."""
+        info = TicketInfo()
         try:
-            self._check(self._L.c2f_wait(self._ctx, ctypes.c_uint64(ticket)))
+            self._check(self._L.c2f_wait_info(self._ctx, ctypes.c_uint64(ticket), ctypes.byref(info)))
         finally:
             res = self._keep.pop(ticket, None)
-        return res
+        return res, {k: getattr(info, k) for k, _ in TicketInfo._fields_}
 
 
 def fbp_coefficients(fuel: int) -> np.ndarray:

@@ -1,6 +1,8 @@
-// libc2f host runtime: device memory, streams, work slots, relaunch on
-// work-list overflow, batching of requests into one launch, hipGraph replay,
-// autotuning, and the asynchronous serving queue.  Implements include/c2f.h.
+// libc2f host runtime: device memory, executors (a stream with its work
+// slots, lists, counters and staging), relaunch on work-list overflow,
+// batching of requests into one launch, hipGraph replay, autotuning, and the
+// serving lanes that run admitted batches concurrently.  Implements
+// include/c2f.h.
 
 #include "../../include/c2f.h"
 
@@ -30,6 +32,10 @@ using namespace c2f;
 
 namespace {
 
+// Message of the most recent failure on the calling thread; copied into the
+// context's error text when an entry point returns.
+thread_local std::string t_err;
+
 struct Landscape {
     int32_t rows = 0, cols = 0, cell_m = 0;
     float pc = 50.f, curing = 80.f;
@@ -37,7 +43,7 @@ struct Landscape {
     CellRec* cells = nullptr;
     int32_t* burnable = nullptr;
     LandDev* land = nullptr;
-    size_t bytes = 0;
+    int32_t inflight = 0;   // submitted requests not yet completed
     int64_t ncells() const { return (int64_t)rows * cols; }
 };
 
@@ -46,7 +52,7 @@ struct Weather {
     float* rows = nullptr;
     double* t64 = nullptr;
     float* t32 = nullptr;
-    size_t bytes = 0;
+    int32_t inflight = 0;
 };
 
 struct TuneKey {
@@ -77,30 +83,21 @@ struct OutPlan {
     int32_t* scen = nullptr;
 };
 
-struct Ticket;
-
-}  // namespace
-
-struct c2f_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    int n_cu = 0;
+// An executor: one HIP stream and the device buffers its launches use.
+// Buffers only grow; a serving lane rounds sizes up to powers of two so that
+// batches of varying shape rarely reallocate.
+struct Exec {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
-    std::string err;
-    std::map<int32_t, Landscape> lands;
-    std::map<int32_t, Weather> weathers;
-    int32_t next_id = 1;
-    size_t bytes_in_use = 0;
+    bool round_up = false;
 
-    // work slots
-    uint32_t* planes = nullptr;
+    uint32_t* planes = nullptr;   // n_slots x plane_cells arrival labels
     int64_t plane_cells = 0;
     int32_t n_slots = 0;
-    uint8_t* lists = nullptr;
+    uint8_t* lists = nullptr;     // list_slots x list_cap x kSlotListBytesPerEntry
     int64_t list_cap = 0;
     int32_t list_slots = 0;
-    uint32_t* tags = nullptr;
+    uint32_t* tags = nullptr;     // tag_slots generation tags
     int32_t tag_slots = 0;
 
     RunCounters* rc = nullptr;
@@ -110,23 +107,71 @@ struct c2f_ctx {
     Job* h_jobs = nullptr;            // pinned
     int32_t h_jobs_cap = 0;
 
-    void* staging = nullptr;
+    void* staging = nullptr;          // device copy of host-bound outputs
     size_t staging_bytes = 0;
-
-    int32_t block_override = 0;
-    int64_t cap_override = 0;
-    std::map<TuneKey, TuneVal> tune;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     c2f_run_stats last{};
 
-    // hipGraph of the last plain launch sequence
+    // hipGraph of the last launch sequence (synchronous calls only)
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     std::vector<uint64_t> graph_key;
     bool graph_unavailable = false;   // capture refused once: launch eagerly
+};
 
-    std::mutex mu;   // serialises device work between API calls and the server thread
+struct Ticket {
+    uint64_t id = 0;
+    c2f_sim_params params{};
+    c2f_outputs out{};
+    Landscape* L = nullptr;
+    Weather* W = nullptr;
+    bool done = false;
+    c2f_status status = C2F_OK;
+    std::string err;
+    c2f_ticket_info info{};
+};
+
+struct Lane {
+    Exec ex;
+    std::thread th;
+    bool busy = false;
+    int32_t index = 0;
+};
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct c2f_ctx {
+    int device = 0;
+    uint64_t budget = 0;        // caller's cap on device bytes (0 = none)
+    uint64_t admit_limit = 0;   // bytes serving admission plans against
+    int n_cu = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex errmu;
+    std::string err;
+
+    std::mutex mu;   // serialises the synchronous entry points; guards `main`
+    Exec main;
+
+    // Landscapes and weather.  Inserting or erasing needs `mu` and `objmu`;
+    // lookups hold either; the in-flight counts need `objmu`.
+    std::mutex objmu;
+    std::map<int32_t, Landscape> lands;
+    std::map<int32_t, Weather> weathers;
+    int32_t next_id = 1;
+
+    std::mutex memmu;   // device-memory ledger
+    size_t bytes_in_use = 0;
+
+    std::mutex tunemu;
+    int32_t block_override = 0;
+    int64_t cap_override = 0;
+    std::map<TuneKey, TuneVal> tune;
 
     // serving
     std::mutex smu;
@@ -134,37 +179,45 @@ struct c2f_ctx {
     std::deque<std::shared_ptr<Ticket>> queue;
     std::map<uint64_t, std::shared_ptr<Ticket>> tickets;
     uint64_t next_ticket = 1;
-    std::thread server;
-    bool stopping = false;
+    std::vector<std::unique_ptr<Lane>> lanes;
+    int32_t n_lanes = 4;
     int32_t max_queue = 4096;
-    int32_t max_batch_items = 1 << 16;
+    int32_t max_batch_reps = 1 << 16;
+    int32_t max_batch_grid = 0;
+    int32_t busy_lanes = 0;
+    size_t promised = 0;   // growth admitted to running lanes, not yet released
+    bool stopping = false;
 };
 
 namespace {
-
-struct Ticket {
-    uint64_t id = 0;
-    c2f_sim_params params{};
-    c2f_outputs out{};
-    bool done = false;
-    c2f_status status = C2F_OK;
-    std::string err;
-    size_t footprint = 0;
-};
 
 // Drop any error left by an earlier runtime call whose status was ignored,
 // so that launch checks (hipGetLastError) report only their own launch.
 inline void clear_sticky_error() { (void)hipGetLastError(); }
 
-c2f_status fail(c2f_ctx* ctx, c2f_status st, const char* fmt, ...) {
+c2f_status fail(c2f_ctx*, c2f_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (ctx) ctx->err = buf;
+    t_err = buf;
     return st;
 }
+
+// Scope of one entry point: starts with a clean error state and publishes
+// the thread's error text to the context on return.
+struct ApiScope {
+    c2f_ctx* ctx;
+    explicit ApiScope(c2f_ctx* c) : ctx(c) {
+        t_err.clear();
+        clear_sticky_error();
+    }
+    ~ApiScope() {
+        std::lock_guard<std::mutex> lk(ctx->errmu);
+        ctx->err = t_err;
+    }
+};
 
 #define HIP_TRY(ctx, expr)                                                                         \
     do {                                                                                           \
@@ -175,16 +228,21 @@ c2f_status fail(c2f_ctx* ctx, c2f_status st, const char* fmt, ...) {
 
 c2f_status dev_alloc(c2f_ctx* ctx, void** p, size_t bytes) {
     if (bytes == 0) bytes = 16;
-    if (ctx->budget && ctx->bytes_in_use + bytes > ctx->budget)
-        return fail(ctx, C2F_ENOMEM, "HBM budget exceeded: %zu in use + %zu requested > %llu", ctx->bytes_in_use,
-                    bytes, (unsigned long long)ctx->budget);
+    {
+        std::lock_guard<std::mutex> lk(ctx->memmu);
+        if (ctx->budget && ctx->bytes_in_use + bytes > ctx->budget)
+            return fail(ctx, C2F_ENOMEM, "HBM budget exceeded: %zu in use + %zu requested > %llu",
+                        ctx->bytes_in_use, bytes, (unsigned long long)ctx->budget);
+        ctx->bytes_in_use += bytes;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;
+        std::lock_guard<std::mutex> lk(ctx->memmu);
+        ctx->bytes_in_use -= std::min(ctx->bytes_in_use, bytes);
         return fail(ctx, C2F_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
-    ctx->bytes_in_use += bytes;
     return C2F_OK;
 }
 
@@ -192,7 +250,13 @@ void dev_free(c2f_ctx* ctx, void* p, size_t bytes) {
     if (!p) return;
     (void)hipFree(p);
     if (bytes == 0) bytes = 16;
+    std::lock_guard<std::mutex> lk(ctx->memmu);
     ctx->bytes_in_use -= std::min(ctx->bytes_in_use, bytes);
+}
+
+size_t bytes_in_use(c2f_ctx* ctx) {
+    std::lock_guard<std::mutex> lk(ctx->memmu);
+    return ctx->bytes_in_use;
 }
 
 int32_t axis_diag(int32_t cs) {
@@ -204,90 +268,192 @@ int32_t axis_diag(int32_t cs) {
     return (int32_t)d;
 }
 
-void drop_graph(c2f_ctx* ctx) {
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+int64_t pow2_at_least(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------- executors
+
+void drop_graph(Exec& ex) {
+    if (ex.graph_exec) (void)hipGraphExecDestroy(ex.graph_exec);
+    if (ex.graph) (void)hipGraphDestroy(ex.graph);
     clear_sticky_error();
-    ctx->graph_exec = nullptr;
-    ctx->graph = nullptr;
-    ctx->graph_key.clear();
+    ex.graph_exec = nullptr;
+    ex.graph = nullptr;
+    ex.graph_key.clear();
 }
 
-// Make sure n slots of plane_cells labels and lists of `cap` entries exist.
-c2f_status ensure_slots(c2f_ctx* ctx, int32_t n, int64_t cells, int64_t cap) {
-    if (n > ctx->n_slots || cells > ctx->plane_cells) {
-        drop_graph(ctx);
-        dev_free(ctx, ctx->planes, (size_t)ctx->n_slots * ctx->plane_cells * 4);
-        ctx->planes = nullptr;
-        const int32_t ns = std::max(n, ctx->n_slots);
-        const int64_t pc = std::max(cells, ctx->plane_cells);
-        ctx->n_slots = 0;
-        ctx->plane_cells = 0;
-        c2f_status st = dev_alloc(ctx, (void**)&ctx->planes, (size_t)ns * pc * 4);
+c2f_status exec_init(c2f_ctx* ctx, Exec& ex, bool round_up) {
+    ex.round_up = round_up;
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ex.own_stream, hipStreamNonBlocking));
+    ex.stream = ex.own_stream;
+    HIP_TRY(ctx, hipEventCreate(&ex.ev0));
+    HIP_TRY(ctx, hipEventCreate(&ex.ev1));
+    c2f_status st = dev_alloc(ctx, (void**)&ex.rc, sizeof(RunCounters));
+    if (st != C2F_OK) return st;
+    HIP_TRY(ctx, hipHostMalloc((void**)&ex.rc_host, sizeof(RunCounters), hipHostMallocDefault));
+    return C2F_OK;
+}
+
+// Free the growable buffers (planes, lists, tags, staging, job table).
+void exec_trim(c2f_ctx* ctx, Exec& ex) {
+    if (ex.stream) (void)hipStreamSynchronize(ex.stream);
+    drop_graph(ex);
+    dev_free(ctx, ex.planes, (size_t)ex.n_slots * ex.plane_cells * 4);
+    dev_free(ctx, ex.lists, (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry);
+    dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
+    dev_free(ctx, ex.staging, ex.staging_bytes);
+    dev_free(ctx, ex.d_jobs, (size_t)ex.d_jobs_cap * sizeof(Job));
+    ex.planes = nullptr;
+    ex.n_slots = 0;
+    ex.plane_cells = 0;
+    ex.lists = nullptr;
+    ex.list_slots = 0;
+    ex.list_cap = 0;
+    ex.tags = nullptr;
+    ex.tag_slots = 0;
+    ex.staging = nullptr;
+    ex.staging_bytes = 0;
+    ex.d_jobs = nullptr;
+    ex.d_jobs_cap = 0;
+}
+
+void exec_release(c2f_ctx* ctx, Exec& ex) {
+    exec_trim(ctx, ex);
+    dev_free(ctx, ex.rc, sizeof(RunCounters));
+    ex.rc = nullptr;
+    if (ex.h_jobs) (void)hipHostFree(ex.h_jobs);
+    if (ex.rc_host) (void)hipHostFree(ex.rc_host);
+    if (ex.ev0) (void)hipEventDestroy(ex.ev0);
+    if (ex.ev1) (void)hipEventDestroy(ex.ev1);
+    if (ex.own_stream) (void)hipStreamDestroy(ex.own_stream);
+    ex.h_jobs = nullptr;
+    ex.h_jobs_cap = 0;
+    ex.rc_host = nullptr;
+    ex.ev0 = ex.ev1 = nullptr;
+    ex.own_stream = ex.stream = nullptr;
+}
+
+// Sizes the slot buffers of `ex` must have to run n slots of `cells` labels
+// with lists of at least `cap` entries.
+struct SlotSizes {
+    int32_t n_slots;
+    int64_t plane_cells;
+    int32_t list_slots;
+    int64_t list_cap;
+    bool grow_planes, grow_lists;
+};
+
+SlotSizes slot_sizes(const Exec& ex, int32_t n, int64_t cells, int64_t cap) {
+    if (ex.round_up) {
+        n = (int32_t)pow2_at_least(n);
+        cells = pow2_at_least(cells);
+        cap = pow2_at_least(cap);
+    }
+    SlotSizes s;
+    s.grow_planes = n > ex.n_slots || cells > ex.plane_cells;
+    s.n_slots = std::max(n, ex.n_slots);
+    s.plane_cells = std::max(cells, ex.plane_cells);
+    s.grow_lists = n > ex.list_slots || cap > ex.list_cap;
+    s.list_slots = std::max(n, ex.list_slots);
+    s.list_cap = std::max(cap, ex.list_cap);
+    return s;
+}
+
+// Device bytes `ex` would add to run n slots of `cells` with lists of
+// `cap` entries, `stage` bytes of output staging and n_jobs requests.
+size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t stage, int32_t n_jobs) {
+    const SlotSizes s = slot_sizes(ex, n, cells, cap);
+    size_t g = 0;
+    if (n_jobs > ex.d_jobs_cap)
+        g += ((size_t)pow2_at_least(std::max(n_jobs, 64)) - (size_t)ex.d_jobs_cap) * sizeof(Job);
+    if (s.grow_planes) {
+        g += (size_t)s.n_slots * s.plane_cells * 4 - (size_t)ex.n_slots * ex.plane_cells * 4;
+        g += (size_t)s.n_slots * 4;
+    }
+    if (s.grow_lists)
+        g += (size_t)s.list_slots * s.list_cap * kSlotListBytesPerEntry -
+             (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry;
+    if (stage > ex.staging_bytes) g += stage - ex.staging_bytes;
+    return g;
+}
+
+c2f_status ensure_slots(c2f_ctx* ctx, Exec& ex, int32_t n, int64_t cells, int64_t cap) {
+    const SlotSizes s = slot_sizes(ex, n, cells, cap);
+    if (s.grow_planes) {
+        drop_graph(ex);
+        dev_free(ctx, ex.planes, (size_t)ex.n_slots * ex.plane_cells * 4);
+        ex.planes = nullptr;
+        ex.n_slots = 0;
+        ex.plane_cells = 0;
+        c2f_status st = dev_alloc(ctx, (void**)&ex.planes, (size_t)s.n_slots * s.plane_cells * 4);
         if (st != C2F_OK) return st;
-        ctx->n_slots = ns;
-        ctx->plane_cells = pc;
-        HIP_TRY(ctx, launch_fill_u32(ctx->planes, (size_t)ns * pc, kPlaneFill, ctx->stream));
+        ex.n_slots = s.n_slots;
+        ex.plane_cells = s.plane_cells;
+        HIP_TRY(ctx, launch_fill_u32(ex.planes, (size_t)s.n_slots * s.plane_cells, kPlaneFill, ex.stream));
         // every slot restarts from a freshly filled plane
-        dev_free(ctx, ctx->tags, (size_t)ctx->tag_slots * 4);
-        ctx->tags = nullptr;
-        ctx->tag_slots = 0;
-        st = dev_alloc(ctx, (void**)&ctx->tags, (size_t)ns * 4);
+        dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
+        ex.tags = nullptr;
+        ex.tag_slots = 0;
+        st = dev_alloc(ctx, (void**)&ex.tags, (size_t)s.n_slots * 4);
         if (st != C2F_OK) return st;
-        ctx->tag_slots = ns;
-        HIP_TRY(ctx, launch_fill_u32(ctx->tags, (size_t)ns, kTagFresh, ctx->stream));
+        ex.tag_slots = s.n_slots;
+        HIP_TRY(ctx, launch_fill_u32(ex.tags, (size_t)s.n_slots, kTagFresh, ex.stream));
     }
-    if (n > ctx->list_slots || cap != ctx->list_cap) {
-        drop_graph(ctx);
-        dev_free(ctx, ctx->lists, (size_t)ctx->list_slots * ctx->list_cap * kSlotListBytesPerEntry);
-        ctx->lists = nullptr;
-        const int32_t ns = std::max(n, ctx->list_slots);
-        ctx->list_slots = 0;
-        ctx->list_cap = 0;
-        c2f_status st = dev_alloc(ctx, (void**)&ctx->lists, (size_t)ns * cap * kSlotListBytesPerEntry);
+    if (s.grow_lists) {
+        drop_graph(ex);
+        dev_free(ctx, ex.lists, (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry);
+        ex.lists = nullptr;
+        ex.list_slots = 0;
+        ex.list_cap = 0;
+        c2f_status st = dev_alloc(ctx, (void**)&ex.lists, (size_t)s.list_slots * s.list_cap * kSlotListBytesPerEntry);
         if (st != C2F_OK) return st;
-        ctx->list_slots = ns;
-        ctx->list_cap = cap;
+        ex.list_slots = s.list_slots;
+        ex.list_cap = s.list_cap;
     }
     return C2F_OK;
 }
 
-c2f_status ensure_jobs(c2f_ctx* ctx, int32_t n) {
-    if (n > ctx->d_jobs_cap) {
-        drop_graph(ctx);
-        dev_free(ctx, ctx->d_jobs, (size_t)ctx->d_jobs_cap * sizeof(Job));
-        ctx->d_jobs = nullptr;
-        ctx->d_jobs_cap = 0;
-        const int32_t cap = std::max(n, 64);
-        c2f_status st = dev_alloc(ctx, (void**)&ctx->d_jobs, (size_t)cap * sizeof(Job));
+c2f_status ensure_jobs(c2f_ctx* ctx, Exec& ex, int32_t n) {
+    if (n > ex.d_jobs_cap) {
+        drop_graph(ex);
+        dev_free(ctx, ex.d_jobs, (size_t)ex.d_jobs_cap * sizeof(Job));
+        ex.d_jobs = nullptr;
+        ex.d_jobs_cap = 0;
+        const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
+        c2f_status st = dev_alloc(ctx, (void**)&ex.d_jobs, (size_t)cap * sizeof(Job));
         if (st != C2F_OK) return st;
-        ctx->d_jobs_cap = cap;
+        ex.d_jobs_cap = cap;
     }
-    if (n > ctx->h_jobs_cap) {
-        if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
-        ctx->h_jobs = nullptr;
-        ctx->h_jobs_cap = 0;
-        const int32_t cap = std::max(n, 64);
-        HIP_TRY(ctx, hipHostMalloc((void**)&ctx->h_jobs, (size_t)cap * sizeof(Job), hipHostMallocDefault));
-        ctx->h_jobs_cap = cap;
+    if (n > ex.h_jobs_cap) {
+        if (ex.h_jobs) (void)hipHostFree(ex.h_jobs);
+        ex.h_jobs = nullptr;
+        ex.h_jobs_cap = 0;
+        const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
+        HIP_TRY(ctx, hipHostMalloc((void**)&ex.h_jobs, (size_t)cap * sizeof(Job), hipHostMallocDefault));
+        ex.h_jobs_cap = cap;
     }
     return C2F_OK;
 }
 
-c2f_status ensure_staging(c2f_ctx* ctx, size_t bytes) {
-    if (bytes > ctx->staging_bytes) {
-        drop_graph(ctx);
-        dev_free(ctx, ctx->staging, ctx->staging_bytes);
-        ctx->staging = nullptr;
-        ctx->staging_bytes = 0;
-        c2f_status st = dev_alloc(ctx, &ctx->staging, bytes);
+c2f_status ensure_staging(c2f_ctx* ctx, Exec& ex, size_t bytes) {
+    if (bytes > ex.staging_bytes) {
+        drop_graph(ex);
+        dev_free(ctx, ex.staging, ex.staging_bytes);
+        ex.staging = nullptr;
+        ex.staging_bytes = 0;
+        c2f_status st = dev_alloc(ctx, &ex.staging, bytes);
         if (st != C2F_OK) return st;
-        ctx->staging_bytes = bytes;
+        ex.staging_bytes = bytes;
     }
     return C2F_OK;
 }
 
-c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, const Landscape** L, const Weather** W) {
+// ---------------------------------------------------------------- requests
+
+c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, Landscape** L, Weather** W) {
     if (!p) return fail(ctx, C2F_EINVAL, "params is NULL");
     auto li = ctx->lands.find(p->landscape_id);
     if (li == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", p->landscape_id);
@@ -314,14 +480,14 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, const Landscape**
     if (p->scenario_mode < 0 || p->scenario_mode > 1) return fail(ctx, C2F_EINVAL, "scenario_mode must be 0 or 1");
     if (p->scenario_mode == 0 && (p->scenario < 0 || p->scenario >= w.n_scen))
         return fail(ctx, C2F_EINVAL, "scenario %d not in 0..%d", p->scenario, w.n_scen - 1);
-    *L = &l;
-    *W = &w;
+    *L = &li->second;
+    *W = &wi->second;
     return C2F_OK;
 }
 
 int64_t default_list_cap(int64_t cells, int32_t reps) {
     // Generous for single large fires, modest when many slots share HBM;
-    // an overflow is detected and the run repeated with twice the capacity.
+    // an overflow is detected and the run repeated with a larger capacity.
     int64_t cap = reps <= 64 ? (int64_t)1 << 20 : (int64_t)1 << 16;
     cap = std::min<int64_t>(cap, std::max<int64_t>(1024, 2 * cells));
     return cap;
@@ -333,29 +499,33 @@ struct LaunchPlan {
     int64_t cap = 1024;
 };
 
-LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t precision) {
+LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t precision, int32_t grid_cap) {
     LaunchPlan lp;
-    auto it = ctx->tune.find(TuneKey{cells, total_items, precision});
-    if (it != ctx->tune.end()) {
-        lp.block = it->second.block;
-        lp.cap = it->second.list_cap;
-    } else {
-        lp.block = cells >= (1 << 22) && total_items <= 16 ? 1024 : 256;
-        lp.cap = default_list_cap(cells, total_items);
+    {
+        std::lock_guard<std::mutex> lk(ctx->tunemu);
+        auto it = ctx->tune.find(TuneKey{cells, total_items, precision});
+        if (it != ctx->tune.end()) {
+            lp.block = it->second.block;
+            lp.cap = it->second.list_cap;
+        } else {
+            lp.block = cells >= (1 << 22) && total_items <= 16 ? 1024 : 256;
+            lp.cap = default_list_cap(cells, total_items);
+        }
+        if (ctx->block_override) lp.block = ctx->block_override;
+        if (ctx->cap_override) lp.cap = ctx->cap_override;
     }
-    if (ctx->block_override) lp.block = ctx->block_override;
-    if (ctx->cap_override) lp.cap = ctx->cap_override;
     int per_cu = propagate_blocks_per_cu(precision, lp.block);
     if (per_cu < 1) per_cu = 1;
     lp.grid = std::max(1, std::min(total_items, per_cu * ctx->n_cu));
+    if (grid_cap > 0) lp.grid = std::min(lp.grid, grid_cap);
     return lp;
 }
 
 // One fused launch over all requests of one precision.  Relaunches with a
 // larger list capacity if any work list overflowed.
-c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vector<c2f_sim_params>& P,
+c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const std::vector<c2f_sim_params>& P,
                      const std::vector<const Landscape*>& Ls, const std::vector<const Weather*>& Ws,
-                     std::vector<OutPlan>& plans, int32_t precision, bool use_graph) {
+                     std::vector<OutPlan>& plans, int32_t precision, bool use_graph, int32_t grid_cap) {
     if (idx.empty()) return C2F_OK;
     int64_t max_cells = 0;
     int32_t total = 0;
@@ -363,12 +533,12 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
         max_cells = std::max(max_cells, Ls[k]->ncells());
         total += P[k].reps;
     }
-    LaunchPlan lp = plan_launch(ctx, max_cells, total, precision);
-    c2f_status st = ensure_jobs(ctx, (int32_t)idx.size());
+    LaunchPlan lp = plan_launch(ctx, max_cells, total, precision, grid_cap);
+    c2f_status st = ensure_jobs(ctx, ex, (int32_t)idx.size());
     if (st != C2F_OK) return st;
 
     for (;;) {
-        st = ensure_slots(ctx, lp.grid, max_cells, lp.cap);
+        st = ensure_slots(ctx, ex, lp.grid, max_cells, lp.cap);
         if (st == C2F_ENOMEM && lp.grid > 1) {
             // fewer resident slots still computes the same result
             lp.grid = std::max(1, lp.grid / 2);
@@ -417,19 +587,20 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
             j.burned = o.burned;
             j.ign_out = o.ign;
             j.scen_out = o.scen;
-            ctx->h_jobs[q] = j;
+            ex.h_jobs[q] = j;
             item += p.reps;
         }
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_jobs, ctx->h_jobs, idx.size() * sizeof(Job), hipMemcpyHostToDevice,
-                                    ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ex.d_jobs, ex.h_jobs, idx.size() * sizeof(Job), hipMemcpyHostToDevice,
+                                    ex.stream));
 
-        Slots sl{ctx->planes, ctx->plane_cells, ctx->lists, ctx->list_cap, ctx->tags};
+        const int64_t limit = std::min(lp.cap, ex.list_cap);
+        Slots sl{ex.planes, ex.plane_cells, ex.lists, ex.list_cap, limit, ex.tags};
         // key of the launch sequence for graph reuse
-        std::vector<uint64_t> key = {(uint64_t)(uintptr_t)ctx->d_jobs, idx.size(), (uint64_t)total,
+        std::vector<uint64_t> key = {(uint64_t)(uintptr_t)ex.d_jobs, idx.size(), (uint64_t)total,
                                      (uint64_t)lp.block, (uint64_t)lp.grid, (uint64_t)precision,
-                                     (uint64_t)(uintptr_t)ctx->planes, (uint64_t)(uintptr_t)ctx->lists,
-                                     (uint64_t)ctx->list_cap, (uint64_t)ctx->plane_cells,
-                                     (uint64_t)(uintptr_t)ctx->stream};
+                                     (uint64_t)(uintptr_t)ex.planes, (uint64_t)(uintptr_t)ex.lists,
+                                     (uint64_t)ex.list_cap, (uint64_t)limit, (uint64_t)ex.plane_cells,
+                                     (uint64_t)(uintptr_t)ex.stream};
         for (int k : idx) {
             key.push_back((uint64_t)(uintptr_t)plans[k].count);
             key.push_back((uint64_t)Ls[k]->ncells());
@@ -437,97 +608,103 @@ c2f_status run_group(c2f_ctx* ctx, const std::vector<int>& idx, const std::vecto
         // fills + propagation; the events bracket this sequence (they are
         // recorded outside any graph capture)
         auto enqueue = [&]() -> hipError_t {
-            hipError_t e = launch_fill_u32((uint32_t*)ctx->rc, sizeof(RunCounters) / 4, 0u, ctx->stream);
+            hipError_t e = launch_fill_u32((uint32_t*)ex.rc, sizeof(RunCounters) / 4, 0u, ex.stream);
             if (e != hipSuccess) return e;
             for (int k : idx) {
                 if (plans[k].count) {
-                    e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->ncells(), 0u, ctx->stream);
+                    e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->ncells(), 0u, ex.stream);
                     if (e != hipSuccess) return e;
                 }
             }
-            return launch_propagate(precision, lp.block, lp.grid, ctx->d_jobs, (int)idx.size(), total, sl,
-                                    ctx->rc, ctx->stream);
+            return launch_propagate(precision, lp.block, lp.grid, ex.d_jobs, (int)idx.size(), total, sl, ex.rc,
+                                    ex.stream);
         };
         bool launched = false;
-        if (use_graph && !ctx->graph_unavailable) {
-            if (ctx->graph_exec == nullptr || ctx->graph_key != key) {
-                drop_graph(ctx);
+        if (use_graph && !ex.graph_unavailable) {
+            if (ex.graph_exec == nullptr || ex.graph_key != key) {
+                drop_graph(ex);
                 hipGraph_t g = nullptr;
-                hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+                hipError_t e = hipStreamBeginCapture(ex.stream, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
                     hipError_t e1 = enqueue();
-                    hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+                    hipError_t e2 = hipStreamEndCapture(ex.stream, &g);
                     e = (e1 != hipSuccess) ? e1 : e2;
                 }
-                if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+                if (e == hipSuccess) e = hipGraphInstantiate(&ex.graph_exec, g, nullptr, nullptr, 0);
                 if (e != hipSuccess) {
                     (void)hipGetLastError();
                     if (g) (void)hipGraphDestroy(g);
-                    ctx->graph_exec = nullptr;
-                    ctx->graph_unavailable = true;
+                    ex.graph_exec = nullptr;
+                    ex.graph_unavailable = true;
                 } else {
-                    ctx->graph = g;
-                    ctx->graph_key = key;
+                    ex.graph = g;
+                    ex.graph_key = key;
                 }
             }
-            if (ctx->graph_exec) {
-                HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-                HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
-                HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            if (ex.graph_exec) {
+                HIP_TRY(ctx, hipEventRecord(ex.ev0, ex.stream));
+                HIP_TRY(ctx, hipGraphLaunch(ex.graph_exec, ex.stream));
+                HIP_TRY(ctx, hipEventRecord(ex.ev1, ex.stream));
                 launched = true;
             }
         }
         if (!launched) {
-            HIP_TRY(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+            HIP_TRY(ctx, hipEventRecord(ex.ev0, ex.stream));
             HIP_TRY(ctx, enqueue());
-            HIP_TRY(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            HIP_TRY(ctx, hipEventRecord(ex.ev1, ex.stream));
         }
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->rc_host, ctx->rc, sizeof(RunCounters), hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ex.rc_host, ex.rc, sizeof(RunCounters), hipMemcpyDeviceToHost, ex.stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
         float ms = 0.f;
-        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        ctx->last.kernel_ms += ms;
-        if (ctx->rc_host->overflow == 0) {
-            ctx->last.entries += (int64_t)ctx->rc_host->c[kCntEntries];
-            ctx->last.rate_evals += (int64_t)ctx->rc_host->c[kCntEvals];
-            ctx->last.candidates += (int64_t)ctx->rc_host->c[kCntCandidates];
-            ctx->last.improvements += (int64_t)ctx->rc_host->c[kCntImprovements];
-            ctx->last.ignitions += (int64_t)ctx->rc_host->c[kCntIgnitions];
-            ctx->last.rounds += (int64_t)ctx->rc_host->c[kCntRounds];
-            ctx->last.continuations += (int64_t)ctx->rc_host->c[kCntConts];
-            ctx->last.block_threads = lp.block;
-            ctx->last.grid_blocks = lp.grid;
-            ctx->last.list_capacity = lp.cap;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ex.ev0, ex.ev1));
+        ex.last.kernel_ms += ms;
+        if (ex.rc_host->overflow == 0) {
+            ex.last.entries += (int64_t)ex.rc_host->c[kCntEntries];
+            ex.last.rate_evals += (int64_t)ex.rc_host->c[kCntEvals];
+            ex.last.candidates += (int64_t)ex.rc_host->c[kCntCandidates];
+            ex.last.improvements += (int64_t)ex.rc_host->c[kCntImprovements];
+            ex.last.ignitions += (int64_t)ex.rc_host->c[kCntIgnitions];
+            ex.last.rounds += (int64_t)ex.rc_host->c[kCntRounds];
+            ex.last.continuations += (int64_t)ex.rc_host->c[kCntConts];
+            ex.last.block_threads = lp.block;
+            ex.last.grid_blocks = lp.grid;
+            ex.last.list_capacity = limit;
             return C2F_OK;
         }
-        ++ctx->last.relaunches;
+        ++ex.last.relaunches;
         const int64_t hard_max = std::min<int64_t>(std::max<int64_t>(4 * max_cells, 1 << 12) * 8, (int64_t)1 << 30);
-        if (lp.cap >= hard_max) return fail(ctx, C2F_ECAPACITY, "work lists overflow at capacity %lld", (long long)lp.cap);
-        lp.cap = std::min(hard_max, lp.cap * 4);
+        if (limit >= hard_max)
+            return fail(ctx, C2F_ECAPACITY, "work lists overflow at capacity %lld", (long long)limit);
+        lp.cap = std::min(hard_max, limit * 4);
         // remember the larger capacity for requests of this shape
+        std::lock_guard<std::mutex> lk(ctx->tunemu);
         ctx->tune[TuneKey{max_cells, total, precision}] = TuneVal{lp.block, lp.cap};
     }
 }
 
-c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* params, const c2f_outputs* outs,
-                         bool use_graph) {
-    if (!ctx) return C2F_EINVAL;
-    if (n_jobs <= 0 || !params || !outs) return fail(ctx, C2F_EINVAL, "need n_jobs >= 1 and params/out arrays");
-    std::vector<c2f_sim_params> P(params, params + n_jobs);
-    std::vector<const Landscape*> Ls(n_jobs);
-    std::vector<const Weather*> Ws(n_jobs);
+// Device bytes of the host-bound outputs of one request.
+size_t host_output_bytes(const c2f_outputs& o, int64_t cells, int32_t reps) {
+    if (o.on_device) return 0;
+    const size_t n = (size_t)cells, r = (size_t)reps;
+    auto sz = [](const void* p, size_t b) -> size_t { return p ? ((b + 255) & ~(size_t)255) : 0; };
+    return sz(o.scar, r * n) + sz(o.arrival_period, r * n * 4) + sz(o.arrival_minute, r * n * 4) +
+           sz(o.burn_count, n * 4) + sz(o.burned_cells, r * 8) + sz(o.ignition_cell, r * 4) +
+           sz(o.scenario, r * 4);
+}
+
+// Run validated requests on one executor and deliver their outputs.
+c2f_status run_requests(c2f_ctx* ctx, Exec& ex, const std::vector<c2f_sim_params>& P,
+                        const std::vector<const Landscape*>& Ls, const std::vector<const Weather*>& Ws,
+                        const c2f_outputs* outs, bool use_graph, int32_t grid_cap) {
+    const int n_jobs = (int)P.size();
     int64_t total_items = 0;
-    for (int k = 0; k < n_jobs; ++k) {
-        c2f_status st = check_params(ctx, &P[k], &Ls[k], &Ws[k]);
-        if (st != C2F_OK) return st;
-        total_items += P[k].reps;
-    }
+    for (int k = 0; k < n_jobs; ++k) total_items += P[k].reps;
     if (total_items > 0x3FFFFFFF) return fail(ctx, C2F_EINVAL, "too many replications in one call");
 
     // plan outputs: device pointers directly, host ones through staging
     std::vector<OutPlan> plans(n_jobs);
     size_t stage = 0;
-    auto need = [&](bool want, size_t bytes) -> size_t {
+    auto need = [&](const void* want, size_t bytes) -> size_t {
         if (!want) return 0;
         const size_t off = stage;
         stage += (bytes + 255) & ~(size_t)255;
@@ -552,9 +729,9 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
                        need(o.scenario, r * 4)};
         }
     }
-    c2f_status st = ensure_staging(ctx, stage);
+    c2f_status st = ensure_staging(ctx, ex, stage);
     if (st != C2F_OK) return st;
-    char* sb = (char*)ctx->staging;
+    char* sb = (char*)ex.staging;
     for (int k = 0; k < n_jobs; ++k) {
         if (outs[k].on_device) continue;
         auto at = [&](size_t off) -> void* { return off ? sb + off - 1 : nullptr; };
@@ -567,13 +744,13 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
         plans[k].scen = (int32_t*)at(offs[k][6]);
     }
 
-    memset(&ctx->last, 0, sizeof ctx->last);
+    memset(&ex.last, 0, sizeof ex.last);
     std::vector<int> g64, g32;
     for (int k = 0; k < n_jobs; ++k) (P[k].precision == 1 ? g32 : g64).push_back(k);
-    if (!g64.empty() && !g32.empty()) use_graph = false;   // one cached graph per context
-    st = run_group(ctx, g64, P, Ls, Ws, plans, 0, use_graph);
+    if (!g64.empty() && !g32.empty()) use_graph = false;   // one cached graph per executor
+    st = run_group(ctx, ex, g64, P, Ls, Ws, plans, 0, use_graph, grid_cap);
     if (st != C2F_OK) return st;
-    st = run_group(ctx, g32, P, Ls, Ws, plans, 1, use_graph);
+    st = run_group(ctx, ex, g32, P, Ls, Ws, plans, 1, use_graph, grid_cap);
     if (st != C2F_OK) return st;
 
     // copy host outputs back
@@ -583,7 +760,7 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
         const size_t n = (size_t)Ls[k]->ncells(), r = (size_t)P[k].reps;
         auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
             if (!dst) return hipSuccess;
-            return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream);
+            return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ex.stream);
         };
         HIP_TRY(ctx, cp(o.scar, plans[k].scar, r * n));
         HIP_TRY(ctx, cp(o.arrival_period, plans[k].arr_period, r * n * 4));
@@ -593,19 +770,204 @@ c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* par
         HIP_TRY(ctx, cp(o.ignition_cell, plans[k].ign, r * 4));
         HIP_TRY(ctx, cp(o.scenario, plans[k].scen, r * 4));
     }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
     return C2F_OK;
 }
 
-size_t request_footprint(const c2f_ctx* ctx, const c2f_sim_params& p) {
-    auto li = ctx->lands.find(p.landscape_id);
-    if (li == ctx->lands.end()) return 0;
-    const size_t n = (size_t)li->second.ncells();
-    // staging of the outputs the serving path may return (counts + per-rep)
-    return n * 4 + (size_t)p.reps * 24;
+// Synchronous path: validate against the maps (caller holds ctx->mu), run
+// on the main executor.
+c2f_status simulate_impl(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* params, const c2f_outputs* outs,
+                         bool use_graph) {
+    if (n_jobs <= 0 || !params || !outs) return fail(ctx, C2F_EINVAL, "need n_jobs >= 1 and params/out arrays");
+    std::vector<c2f_sim_params> P(params, params + n_jobs);
+    std::vector<const Landscape*> Ls(n_jobs);
+    std::vector<const Weather*> Ws(n_jobs);
+    for (int k = 0; k < n_jobs; ++k) {
+        Landscape* L;
+        Weather* W;
+        c2f_status st = check_params(ctx, &P[k], &L, &W);
+        if (st != C2F_OK) return st;
+        Ls[k] = L;
+        Ws[k] = W;
+    }
+    return run_requests(ctx, ctx->main, P, Ls, Ws, outs, use_graph, 0);
 }
 
-void server_loop(c2f_ctx* ctx);
+// ---------------------------------------------------------------- serving
+
+// Device bytes lane `ex` would add to run `batch`.
+size_t batch_growth(c2f_ctx* ctx, const Exec& ex, const std::vector<std::shared_ptr<Ticket>>& batch) {
+    int64_t cells[2] = {0, 0};
+    int32_t items[2] = {0, 0};
+    size_t stage = 0;
+    for (const auto& t : batch) {
+        const int pr = t->params.precision == 1 ? 1 : 0;
+        cells[pr] = std::max(cells[pr], t->L->ncells());
+        items[pr] += t->params.reps;
+        stage += host_output_bytes(t->out, t->L->ncells(), t->params.reps);
+    }
+    int32_t grid = 1;
+    int64_t cap = 1, max_cells = 1;
+    for (int pr = 0; pr < 2; ++pr) {
+        if (!items[pr]) continue;
+        const LaunchPlan lp = plan_launch(ctx, cells[pr], items[pr], pr, ctx->max_batch_grid);
+        grid = std::max(grid, lp.grid);
+        cap = std::max(cap, lp.cap);
+        max_cells = std::max(max_cells, cells[pr]);
+    }
+    return exec_growth(ex, grid, max_cells, cap, stage, (int32_t)batch.size());
+}
+
+bool fits(c2f_ctx* ctx, size_t growth) {
+    return bytes_in_use(ctx) + ctx->promised + growth <= ctx->admit_limit;
+}
+
+// Form the next batch for `ln` from the head of the queue (caller holds
+// smu).  Requests are taken in arrival order while the lane's added device
+// memory fits the admission limit; a head that does not fit waits for
+// running lanes, and idle lanes give back their buffers to make room.
+bool try_admit(c2f_ctx* ctx, Lane& ln, std::vector<std::shared_ptr<Ticket>>& batch, size_t& growth) {
+    batch.clear();
+    growth = 0;
+    if (ctx->queue.empty()) return false;
+    int64_t items = 0;
+    for (auto it = ctx->queue.begin(); it != ctx->queue.end(); ++it) {
+        const auto& t = *it;
+        if (!batch.empty() && items + t->params.reps > ctx->max_batch_reps) break;
+        batch.push_back(t);
+        const size_t g = batch_growth(ctx, ln.ex, batch);
+        if (!fits(ctx, g)) {
+            batch.pop_back();
+            break;
+        }
+        growth = g;
+        items += t->params.reps;
+    }
+    if (batch.empty()) {
+        // make room: idle lanes release their buffers
+        for (auto& other : ctx->lanes)
+            if (other.get() != &ln && !other->busy) exec_trim(ctx, other->ex);
+        batch.push_back(ctx->queue.front());
+        size_t g = batch_growth(ctx, ln.ex, batch);
+        if (!fits(ctx, g)) {
+            if (ctx->busy_lanes > 0) {
+                batch.clear();
+                return false;   // wait for running batches to finish
+            }
+            // alone on the device: start from empty buffers and let the
+            // launch shrink its grid if memory is short
+            exec_trim(ctx, ln.ex);
+            g = batch_growth(ctx, ln.ex, batch);
+        }
+        growth = g;
+    }
+    ctx->queue.erase(ctx->queue.begin(), ctx->queue.begin() + (ptrdiff_t)batch.size());
+    return true;
+}
+
+void lane_loop(c2f_ctx* ctx, Lane* ln) {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        std::vector<std::shared_ptr<Ticket>> batch;
+        size_t growth = 0;
+        {
+            std::unique_lock<std::mutex> lk(ctx->smu);
+            for (;;) {
+                if (ctx->stopping && ctx->queue.empty()) return;
+                if (try_admit(ctx, *ln, batch, growth)) break;
+                ctx->scv.wait(lk);
+            }
+            ln->busy = true;
+            ++ctx->busy_lanes;
+            ctx->promised += growth;
+        }
+        const double t_start = ms_since(ctx->t0);
+        int32_t items = 0;
+        std::vector<c2f_sim_params> P;
+        std::vector<const Landscape*> Ls;
+        std::vector<const Weather*> Ws;
+        std::vector<c2f_outputs> O;
+        for (auto& t : batch) {
+            P.push_back(t->params);
+            Ls.push_back(t->L);
+            Ws.push_back(t->W);
+            O.push_back(t->out);
+            items += t->params.reps;
+        }
+        t_err.clear();
+        clear_sticky_error();
+        std::vector<c2f_status> st(batch.size());
+        std::vector<std::string> err(batch.size());
+        std::vector<double> kms(batch.size());
+        c2f_status s0 = run_requests(ctx, ln->ex, P, Ls, Ws, O.data(), false, ctx->max_batch_grid);
+        if (s0 == C2F_OK || batch.size() == 1) {
+            for (size_t k = 0; k < batch.size(); ++k) {
+                st[k] = s0;
+                err[k] = t_err;
+                kms[k] = ln->ex.last.kernel_ms;
+            }
+        } else {
+            // run one by one so that a failing request only fails itself
+            for (size_t k = 0; k < batch.size(); ++k) {
+                t_err.clear();
+                clear_sticky_error();
+                std::vector<c2f_sim_params> P1{P[k]};
+                std::vector<const Landscape*> L1{Ls[k]};
+                std::vector<const Weather*> W1{Ws[k]};
+                st[k] = run_requests(ctx, ln->ex, P1, L1, W1, &O[k], false, ctx->max_batch_grid);
+                err[k] = t_err;
+                kms[k] = ln->ex.last.kernel_ms;
+            }
+        }
+        const double t_done = ms_since(ctx->t0);
+        {
+            std::lock_guard<std::mutex> lk(ctx->objmu);
+            for (auto& t : batch) {
+                --t->L->inflight;
+                --t->W->inflight;
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(ctx->smu);
+            ctx->promised -= std::min(ctx->promised, growth);
+            ln->busy = false;
+            --ctx->busy_lanes;
+            for (size_t k = 0; k < batch.size(); ++k) {
+                Ticket& t = *batch[k];
+                t.status = st[k];
+                t.err = err[k];
+                t.info.start_ms = t_start;
+                t.info.done_ms = t_done;
+                t.info.kernel_ms = kms[k];
+                t.info.batch_requests = (int32_t)batch.size();
+                t.info.batch_reps = items;
+                t.info.lane = ln->index;
+                t.info.status = st[k];
+                t.done = true;
+            }
+        }
+        ctx->scv.notify_all();
+    }
+}
+
+// Start the serving lanes (caller holds smu).
+c2f_status start_lanes(c2f_ctx* ctx) {
+    if (!ctx->lanes.empty()) return C2F_OK;
+    for (int32_t i = 0; i < ctx->n_lanes; ++i) {
+        std::unique_ptr<Lane> ln(new Lane());
+        ln->index = i;
+        c2f_status st = exec_init(ctx, ln->ex, true);
+        if (st != C2F_OK) {
+            exec_release(ctx, ln->ex);
+            for (auto& l : ctx->lanes) exec_release(ctx, l->ex);
+            ctx->lanes.clear();
+            return st;
+        }
+        ctx->lanes.push_back(std::move(ln));
+    }
+    for (auto& ln : ctx->lanes) ln->th = std::thread(lane_loop, ctx, ln.get());
+    return C2F_OK;
+}
 
 }  // namespace
 
@@ -626,16 +988,18 @@ c2f_status c2f_create(int32_t device, uint64_t hbm_budget_bytes, c2f_ctx** out) 
     std::unique_ptr<c2f_ctx> ctx(new c2f_ctx());
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
+    ctx->t0 = std::chrono::steady_clock::now();
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return C2F_EDEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return C2F_EDEVICE;
     ctx->n_cu = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) return C2F_EDEVICE;
-    ctx->stream = ctx->own_stream;
-    if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) return C2F_EDEVICE;
-    if (dev_alloc(ctx.get(), (void**)&ctx->rc, sizeof(RunCounters)) != C2F_OK) return C2F_ENOMEM;
-    if (hipHostMalloc((void**)&ctx->rc_host, sizeof(RunCounters), hipHostMallocDefault) != hipSuccess)
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C2F_EDEVICE;
+    ctx->admit_limit = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+    if (exec_init(ctx.get(), ctx->main, false) != C2F_OK) {
+        exec_release(ctx.get(), ctx->main);
         return C2F_EDEVICE;
+    }
     *out = ctx.release();
     return C2F_OK;
 }
@@ -647,10 +1011,12 @@ void c2f_destroy(c2f_ctx* ctx) {
         ctx->stopping = true;
     }
     ctx->scv.notify_all();
-    if (ctx->server.joinable()) ctx->server.join();
+    for (auto& ln : ctx->lanes)
+        if (ln->th.joinable()) ln->th.join();
     (void)hipSetDevice(ctx->device);
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    drop_graph(ctx);
+    for (auto& ln : ctx->lanes) exec_release(ctx, ln->ex);
+    ctx->lanes.clear();
+    exec_release(ctx, ctx->main);
     for (auto& kv : ctx->lands) {
         (void)hipFree(kv.second.fuel);
         (void)hipFree(kv.second.cells);
@@ -662,17 +1028,6 @@ void c2f_destroy(c2f_ctx* ctx) {
         (void)hipFree(kv.second.t64);
         (void)hipFree(kv.second.t32);
     }
-    (void)hipFree(ctx->planes);
-    (void)hipFree(ctx->lists);
-    (void)hipFree(ctx->tags);
-    (void)hipFree(ctx->rc);
-    (void)hipFree(ctx->d_jobs);
-    (void)hipFree(ctx->staging);
-    if (ctx->h_jobs) (void)hipHostFree(ctx->h_jobs);
-    if (ctx->rc_host) (void)hipHostFree(ctx->rc_host);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
 }
 
@@ -680,19 +1035,18 @@ const char* c2f_last_error(const c2f_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 c2f_status c2f_set_stream(c2f_ctx* ctx, void* hip_stream) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    drop_graph(ctx);
-    ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own_stream;
+    drop_graph(ctx->main);
+    ctx->main.stream = hip_stream ? (hipStream_t)hip_stream : ctx->main.own_stream;
     return C2F_OK;
 }
 
 c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
                               const int16_t* elev_m, float pc_pct, float curing_pct, int32_t* landscape_id) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
     if (rows <= 0 || cols <= 0 || (int64_t)rows * cols > 0x7FFFFFFEll)
         return fail(ctx, C2F_EINVAL, "grid %d x %d out of range", rows, cols);
     if (cell_m < 1 || cell_m > 20000) return fail(ctx, C2F_EINVAL, "cell_m %d not in 1..20000", cell_m);
@@ -703,6 +1057,7 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     for (int64_t i = 0; i < n; ++i)
         if (fuel[i] > 15) return fail(ctx, C2F_EINVAL, "fuel code %d at cell %lld > 15", fuel[i], (long long)i);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->main.stream;
     Landscape L;
     L.rows = rows;
     L.cols = cols;
@@ -730,14 +1085,14 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
         cleanup();
         return st;
     }
-    hipError_t e = hipMemcpyAsync(L.fuel, fuel, (size_t)n, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess && elev_m) e = hipMemcpyAsync(d_elev, elev_m, (size_t)n * 2, hipMemcpyHostToDevice, ctx->stream);
+    hipError_t e = hipMemcpyAsync(L.fuel, fuel, (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && elev_m) e = hipMemcpyAsync(d_elev, elev_m, (size_t)n * 2, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_prepare_landscape(L.fuel, d_elev, rows, cols, cell_m, pc_pct, curing_pct, L.cells, L.burnable,
-                                     d_tiles, L.land, ctx->stream);
+                                     d_tiles, L.land, s);
     LandDev hl;
-    if (e == hipSuccess) e = hipMemcpyAsync(&hl, L.land, sizeof hl, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hl, L.land, sizeof hl, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     dev_free(ctx, d_elev, (size_t)n * 2);
     d_elev = nullptr;
     dev_free(ctx, d_tiles, (size_t)n_tiles * 4);
@@ -750,7 +1105,7 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
         cleanup();
         return fail(ctx, C2F_EINVAL, "elevation too steep: a Horn gradient numerator exceeds 32767");
     }
-    L.bytes = (size_t)n * (1 + sizeof(CellRec) + 4) + sizeof(LandDev);
+    std::lock_guard<std::mutex> lk2(ctx->objmu);
     const int32_t id = ctx->next_id++;
     ctx->lands[id] = L;
     *landscape_id = id;
@@ -759,28 +1114,34 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
 
 c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    auto it = ctx->lands.find(landscape_id);
-    if (it == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", landscape_id);
-    (void)hipStreamSynchronize(ctx->stream);
-    drop_graph(ctx);
-    Landscape& L = it->second;
+    Landscape L;
+    {
+        std::lock_guard<std::mutex> lk2(ctx->objmu);
+        auto it = ctx->lands.find(landscape_id);
+        if (it == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", landscape_id);
+        if (it->second.inflight > 0)
+            return fail(ctx, C2F_EBUSY, "landscape %d is used by %d submitted requests", landscape_id,
+                        it->second.inflight);
+        L = it->second;
+        ctx->lands.erase(it);
+    }
+    (void)hipStreamSynchronize(ctx->main.stream);
+    drop_graph(ctx->main);
     const size_t n = (size_t)L.ncells();
     dev_free(ctx, L.fuel, n);
     dev_free(ctx, L.cells, n * sizeof(CellRec));
     dev_free(ctx, L.burnable, n * 4);
     dev_free(ctx, L.land, sizeof(LandDev));
-    ctx->lands.erase(it);
     return C2F_OK;
 }
 
 c2f_status c2f_set_weather(c2f_ctx* ctx, int32_t n_scen, int32_t n_periods, int32_t period_min,
                            const c2f_weather_row* rows, int32_t* weather_id) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
     if (n_scen <= 0 || n_periods <= 0 || period_min <= 0 || !rows || !weather_id)
         return fail(ctx, C2F_EINVAL, "need n_scen, n_periods, period_min >= 1 and non-NULL rows/weather_id");
     if ((int64_t)n_scen * n_periods > (1 << 26)) return fail(ctx, C2F_EINVAL, "weather table too large");
@@ -792,6 +1153,7 @@ c2f_status c2f_set_weather(c2f_ctx* ctx, int32_t n_scen, int32_t n_periods, int3
             return fail(ctx, C2F_EINVAL, "weather row %lld out of range", (long long)i);
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->main.stream;
     Weather W;
     W.n_scen = n_scen;
     W.n_periods = n_periods;
@@ -807,16 +1169,16 @@ c2f_status c2f_set_weather(c2f_ctx* ctx, int32_t n_scen, int32_t n_periods, int3
         dev_free(ctx, W.t64, (size_t)nr * kRowLen * 8);
         return st;
     }
-    hipError_t e = hipMemcpyAsync(W.rows, rows, (size_t)nr * 16, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = launch_weather_table(W.rows, (int)nr, W.t64, W.t32, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    hipError_t e = hipMemcpyAsync(W.rows, rows, (size_t)nr * 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_weather_table(W.rows, (int)nr, W.t64, W.t32, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         dev_free(ctx, W.rows, (size_t)nr * 16);
         dev_free(ctx, W.t64, (size_t)nr * kRowLen * 8);
         dev_free(ctx, W.t32, (size_t)nr * kRowLen * 4);
         return fail(ctx, C2F_EDEVICE, "weather upload failed: %s", hipGetErrorString(e));
     }
-    W.bytes = (size_t)nr * (16 + kRowLen * 12);
+    std::lock_guard<std::mutex> lk2(ctx->objmu);
     const int32_t id = ctx->next_id++;
     ctx->weathers[id] = W;
     *weather_id = id;
@@ -825,35 +1187,40 @@ c2f_status c2f_set_weather(c2f_ctx* ctx, int32_t n_scen, int32_t n_periods, int3
 
 c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    auto it = ctx->weathers.find(weather_id);
-    if (it == ctx->weathers.end()) return fail(ctx, C2F_ESTATE, "unknown weather id %d", weather_id);
-    (void)hipStreamSynchronize(ctx->stream);
-    drop_graph(ctx);
-    Weather& W = it->second;
+    Weather W;
+    {
+        std::lock_guard<std::mutex> lk2(ctx->objmu);
+        auto it = ctx->weathers.find(weather_id);
+        if (it == ctx->weathers.end()) return fail(ctx, C2F_ESTATE, "unknown weather id %d", weather_id);
+        if (it->second.inflight > 0)
+            return fail(ctx, C2F_EBUSY, "weather %d is used by %d submitted requests", weather_id,
+                        it->second.inflight);
+        W = it->second;
+        ctx->weathers.erase(it);
+    }
+    (void)hipStreamSynchronize(ctx->main.stream);
+    drop_graph(ctx->main);
     const size_t nr = (size_t)W.n_scen * W.n_periods;
     dev_free(ctx, W.rows, nr * 16);
     dev_free(ctx, W.t64, nr * kRowLen * 8);
     dev_free(ctx, W.t32, nr * kRowLen * 4);
-    ctx->weathers.erase(it);
     return C2F_OK;
 }
 
 c2f_status c2f_simulate(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
     return simulate_impl(ctx, 1, params, out, true);
 }
 
 c2f_status c2f_simulate_batch(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* params, const c2f_outputs* out) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
     return simulate_impl(ctx, n_jobs, params, out, true);
 }
@@ -862,9 +1229,8 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
                         int32_t rep, uint64_t seed, float sigma, int32_t rounding, int32_t precision, double* hros,
                         double* bros, double* fros, double* lb, double* raz_deg, double* x8, int32_t* q8) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
     auto li = ctx->lands.find(landscape_id);
     if (li == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", landscape_id);
     auto wi = ctx->weathers.find(weather_id);
@@ -877,11 +1243,12 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
         (precision != 0 && precision != 1))
         return fail(ctx, C2F_EINVAL, "bad sigma/rounding/precision");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Exec& ex = ctx->main;
     const size_t n = (size_t)L.ncells();
     const size_t bytes = n * 8 * 5 + n * 64 + n * 32 + 7 * 256;   // 7 arrays, 256-byte aligned
-    c2f_status st = ensure_staging(ctx, bytes);
+    c2f_status st = ensure_staging(ctx, ex, bytes);
     if (st != C2F_OK) return st;
-    char* sb = (char*)ctx->staging;
+    char* sb = (char*)ex.staging;
     EvalArgs a;
     memset(&a, 0, sizeof a);
     a.cells = L.cells;
@@ -909,15 +1276,15 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
     a.raz = raz_deg ? (double*)take(n * 8) : nullptr;
     a.x8 = x8 ? (double*)take(n * 64) : nullptr;
     a.q8 = q8 ? (int32_t*)take(n * 32) : nullptr;
-    HIP_TRY(ctx, launch_eval_ros(precision, a, ctx->stream));
-    if (hros) HIP_TRY(ctx, hipMemcpyAsync(hros, a.hros, n * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (bros) HIP_TRY(ctx, hipMemcpyAsync(bros, a.bros, n * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (fros) HIP_TRY(ctx, hipMemcpyAsync(fros, a.fros, n * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (lb) HIP_TRY(ctx, hipMemcpyAsync(lb, a.lb, n * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (raz_deg) HIP_TRY(ctx, hipMemcpyAsync(raz_deg, a.raz, n * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if (x8) HIP_TRY(ctx, hipMemcpyAsync(x8, a.x8, n * 64, hipMemcpyDeviceToHost, ctx->stream));
-    if (q8) HIP_TRY(ctx, hipMemcpyAsync(q8, a.q8, n * 32, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, launch_eval_ros(precision, a, ex.stream));
+    if (hros) HIP_TRY(ctx, hipMemcpyAsync(hros, a.hros, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (bros) HIP_TRY(ctx, hipMemcpyAsync(bros, a.bros, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (fros) HIP_TRY(ctx, hipMemcpyAsync(fros, a.fros, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (lb) HIP_TRY(ctx, hipMemcpyAsync(lb, a.lb, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (raz_deg) HIP_TRY(ctx, hipMemcpyAsync(raz_deg, a.raz, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (x8) HIP_TRY(ctx, hipMemcpyAsync(x8, a.x8, n * 64, hipMemcpyDeviceToHost, ex.stream));
+    if (q8) HIP_TRY(ctx, hipMemcpyAsync(q8, a.q8, n * 32, hipMemcpyDeviceToHost, ex.stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
     return C2F_OK;
 }
 
@@ -934,13 +1301,13 @@ c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]) {
 
 c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capacity) {
     if (!ctx) return C2F_EINVAL;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
+    ApiScope api(ctx);
     if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
         block_threads != 512 && block_threads != 1024)
         return fail(ctx, C2F_EINVAL, "block_threads must be 0 or one of 64,128,256,512,1024");
     if (list_capacity < 0 || list_capacity > ((int64_t)1 << 30))
         return fail(ctx, C2F_EINVAL, "list_capacity out of range");
+    std::lock_guard<std::mutex> lk(ctx->tunemu);
     ctx->block_override = block_threads;
     ctx->cap_override = list_capacity;
     return C2F_OK;
@@ -948,14 +1315,14 @@ c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capa
 
 c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* rep) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-    ctx->err.clear();
-    const Landscape* L;
-    const Weather* W;
+    Landscape* L;
+    Weather* W;
     c2f_status st = check_params(ctx, rep, &L, &W);
     if (st != C2F_OK) return st;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Exec& ex = ctx->main;
     const int64_t n = L->ncells();
     uint32_t* counts = nullptr;
     st = dev_alloc(ctx, (void**)&counts, (size_t)n * 4);
@@ -964,68 +1331,127 @@ c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* rep) {
     memset(&o, 0, sizeof o);
     o.burn_count = counts;
     o.on_device = 1;
-    const int32_t saved_block = ctx->block_override;
-    const int64_t saved_cap = ctx->cap_override;
+    int32_t saved_block;
+    int64_t saved_cap;
+    auto set_over = [&](int32_t b, int64_t c) {
+        std::lock_guard<std::mutex> lk2(ctx->tunemu);
+        ctx->block_override = b;
+        ctx->cap_override = c;
+    };
+    {
+        std::lock_guard<std::mutex> lk2(ctx->tunemu);
+        saved_block = ctx->block_override;
+        saved_cap = ctx->cap_override;
+    }
     // first run at the default settings finds the list high-water mark
-    ctx->block_override = 0;
-    ctx->cap_override = 0;
+    set_over(0, 0);
     st = simulate_impl(ctx, 1, rep, &o, false);
-    int64_t cap = ctx->last.list_capacity;
-    const int64_t hw = (int64_t)ctx->rc_host->c[kCntMaxList];
+    int64_t cap = ex.last.list_capacity;
+    const int64_t hw = (int64_t)ex.rc_host->c[kCntMaxList];
     if (st == C2F_OK && hw > 0) cap = std::max<int64_t>(1024, std::min<int64_t>(cap, 4 * hw));
     int32_t best_block = 256;
     double best_ms = 1e30;
     const int blocks[5] = {64, 128, 256, 512, 1024};
     for (int b = 0; b < 5 && st == C2F_OK; ++b) {
-        ctx->block_override = blocks[b];
-        ctx->cap_override = cap;
+        set_over(blocks[b], cap);
         double ms_sum = 0;
         for (int t = 0; t < 2 && st == C2F_OK; ++t) {
             st = simulate_impl(ctx, 1, rep, &o, false);
-            ms_sum += ctx->last.kernel_ms;
-            if (ctx->last.relaunches) cap = ctx->last.list_capacity;
+            ms_sum += ex.last.kernel_ms;
+            if (ex.last.relaunches) cap = ex.last.list_capacity;
         }
         if (st == C2F_OK && ms_sum < best_ms) {
             best_ms = ms_sum;
             best_block = blocks[b];
         }
     }
-    ctx->block_override = saved_block;
-    ctx->cap_override = saved_cap;
+    set_over(saved_block, saved_cap);
     dev_free(ctx, counts, (size_t)n * 4);
     if (st != C2F_OK) return st;
+    std::lock_guard<std::mutex> lk2(ctx->tunemu);
     ctx->tune[TuneKey{n, rep->reps, rep->precision}] = TuneVal{best_block, cap};
     return C2F_OK;
 }
 
 c2f_status c2f_get_stats(const c2f_ctx* ctx, c2f_run_stats* out) {
     if (!ctx || !out) return C2F_EINVAL;
-    *out = ctx->last;
+    *out = ctx->main.last;
     return C2F_OK;
 }
 
 // ------------------------------------------------------------- serving
 
+c2f_status c2f_set_serving(c2f_ctx* ctx, int32_t lanes, int32_t max_batch_reps, int32_t max_batch_grid,
+                           uint64_t admit_bytes) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (ctx->budget && admit_bytes > ctx->budget)
+        return fail(ctx, C2F_EINVAL, "admit_bytes exceeds the context's budget");
+    if (lanes < 1 || lanes > 16) return fail(ctx, C2F_EINVAL, "lanes must be in 1..16");
+    if (max_batch_reps < 1) return fail(ctx, C2F_EINVAL, "max_batch_reps must be >= 1");
+    if (max_batch_grid < 0) return fail(ctx, C2F_EINVAL, "max_batch_grid must be >= 0");
+    std::lock_guard<std::mutex> lk(ctx->smu);
+    if (!ctx->lanes.empty()) return fail(ctx, C2F_ESTATE, "serving already started");
+    ctx->n_lanes = lanes;
+    ctx->max_batch_reps = max_batch_reps;
+    ctx->max_batch_grid = max_batch_grid;
+    if (admit_bytes) ctx->admit_limit = admit_bytes;
+    return C2F_OK;
+}
+
+c2f_status c2f_get_memory(c2f_ctx* ctx, uint64_t* bytes_held, uint64_t* admit_limit) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (!bytes_held || !admit_limit) return fail(ctx, C2F_EINVAL, "outputs must be non-NULL");
+    *bytes_held = bytes_in_use(ctx);
+    std::lock_guard<std::mutex> lk(ctx->smu);
+    *admit_limit = ctx->admit_limit;
+    return C2F_OK;
+}
+
 c2f_status c2f_submit(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out, uint64_t* ticket) {
-    if (!ctx || !params || !out || !ticket) return C2F_EINVAL;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-        const Landscape* L;
-        const Weather* W;
-        c2f_status st = check_params(ctx, params, &L, &W);
-        if (st != C2F_OK) return st;
-    }
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (!params || !out || !ticket) return fail(ctx, C2F_EINVAL, "params, out and ticket must be non-NULL");
     auto t = std::make_shared<Ticket>();
     t->params = *params;
     t->out = *out;
     {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        c2f_status st = check_params(ctx, params, &t->L, &t->W);
+        if (st != C2F_OK) return st;
+        std::lock_guard<std::mutex> lk2(ctx->objmu);
+        ++t->L->inflight;
+        ++t->W->inflight;
+    }
+    auto release = [&]() {
+        std::lock_guard<std::mutex> lk(ctx->objmu);
+        --t->L->inflight;
+        --t->W->inflight;
+    };
+    {
         std::lock_guard<std::mutex> lk(ctx->smu);
-        if ((int32_t)ctx->queue.size() >= ctx->max_queue) return fail(ctx, C2F_EBUSY, "serving queue full");
+        if ((int32_t)ctx->queue.size() >= ctx->max_queue) {
+            release();
+            return fail(ctx, C2F_EBUSY, "serving queue full (%d waiting)", ctx->max_queue);
+        }
+        if (ctx->stopping) {
+            release();
+            return fail(ctx, C2F_ESTATE, "context is being destroyed");
+        }
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            release();
+            return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
+        }
+        c2f_status st = start_lanes(ctx);
+        if (st != C2F_OK) {
+            release();
+            return st;
+        }
         t->id = ctx->next_ticket++;
+        t->info.submit_ms = ms_since(ctx->t0);
         ctx->tickets[t->id] = t;
         ctx->queue.push_back(t);
-        if (!ctx->server.joinable()) ctx->server = std::thread(server_loop, ctx);
     }
     ctx->scv.notify_all();
     *ticket = t->id;
@@ -1033,86 +1459,30 @@ c2f_status c2f_submit(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outp
 }
 
 c2f_status c2f_poll(c2f_ctx* ctx, uint64_t ticket, int32_t* done) {
-    if (!ctx || !done) return C2F_EINVAL;
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (!done) return fail(ctx, C2F_EINVAL, "done must be non-NULL");
     std::lock_guard<std::mutex> lk(ctx->smu);
     auto it = ctx->tickets.find(ticket);
-    if (it == ctx->tickets.end()) return C2F_ESTATE;
+    if (it == ctx->tickets.end()) return fail(ctx, C2F_ESTATE, "unknown ticket %llu", (unsigned long long)ticket);
     *done = it->second->done ? 1 : 0;
     return C2F_OK;
 }
 
-c2f_status c2f_wait(c2f_ctx* ctx, uint64_t ticket) {
+c2f_status c2f_wait_info(c2f_ctx* ctx, uint64_t ticket, c2f_ticket_info* info) {
     if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
     std::unique_lock<std::mutex> lk(ctx->smu);
     auto it = ctx->tickets.find(ticket);
-    if (it == ctx->tickets.end()) return C2F_ESTATE;
+    if (it == ctx->tickets.end()) return fail(ctx, C2F_ESTATE, "unknown ticket %llu", (unsigned long long)ticket);
     std::shared_ptr<Ticket> t = it->second;
     ctx->scv.wait(lk, [&] { return t->done; });
-    const c2f_status st = t->status;
-    if (st != C2F_OK) ctx->err = t->err;
     ctx->tickets.erase(ticket);
-    return st;
+    if (info) *info = t->info;
+    if (t->status != C2F_OK) return fail(ctx, t->status, "%s", t->err.c_str());
+    return C2F_OK;
 }
+
+c2f_status c2f_wait(c2f_ctx* ctx, uint64_t ticket) { return c2f_wait_info(ctx, ticket, nullptr); }
 
 }  // extern "C"
-
-namespace {
-
-// Serving loop: take every waiting request whose memory fits, run them as
-// one fused launch, complete their tickets, repeat.  Requests that arrive
-// while a batch is on the device join the next batch.
-void server_loop(c2f_ctx* ctx) {
-    (void)hipSetDevice(ctx->device);
-    for (;;) {
-        std::vector<std::shared_ptr<Ticket>> batch;
-        {
-            std::unique_lock<std::mutex> lk(ctx->smu);
-            ctx->scv.wait(lk, [&] { return ctx->stopping || !ctx->queue.empty(); });
-            if (ctx->stopping && ctx->queue.empty()) return;
-            int64_t items = 0;
-            while (!ctx->queue.empty()) {
-                auto& t = ctx->queue.front();
-                if (!batch.empty() && items + t->params.reps > ctx->max_batch_items) break;
-                items += t->params.reps;
-                batch.push_back(t);
-                ctx->queue.pop_front();
-            }
-        }
-        std::vector<c2f_sim_params> P;
-        std::vector<c2f_outputs> O;
-        for (auto& t : batch) {
-            P.push_back(t->params);
-            O.push_back(t->out);
-        }
-        c2f_status st;
-        std::string err;
-        {
-            std::lock_guard<std::mutex> lk(ctx->mu);
-    clear_sticky_error();
-            st = simulate_impl(ctx, (int32_t)P.size(), P.data(), O.data(), false);
-            err = ctx->err;
-            if (st != C2F_OK && P.size() > 1) {
-                // run one by one so a bad request only fails itself
-                for (size_t k = 0; k < P.size(); ++k) {
-                    c2f_status s1 = simulate_impl(ctx, 1, &P[k], &O[k], false);
-                    std::lock_guard<std::mutex> lk2(ctx->smu);
-                    batch[k]->status = s1;
-                    batch[k]->err = ctx->err;
-                }
-            }
-        }
-        {
-            std::lock_guard<std::mutex> lk(ctx->smu);
-            for (auto& t : batch) {
-                if (!(st != C2F_OK && P.size() > 1)) {
-                    t->status = st;
-                    t->err = err;
-                }
-                t->done = true;
-            }
-        }
-        ctx->scv.notify_all();
-    }
-}
-
-}  // namespace

@@ -143,10 +143,12 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
     return evals;
 }
 
-// At least 4 waves per SIMD (<= 128 VGPRs): the kernel is latency bound,
-// so resident replications matter more than registers.
+// At least 2 waves per SIMD (<= 256 VGPRs).  A tighter bound (4 waves,
+// 128 VGPRs) doubles the resident replications but spills several hundred
+// bytes per lane to scratch in every pass, and measured slower; a 1024-thread
+// group needs 4 waves per SIMD anyway and keeps 128.
 template <typename R, int BLOCK>
-__global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restrict__ jobs, int n_jobs,
+__global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restrict__ jobs, int n_jobs,
                                                           int total_items, Slots slots,
                                                           RunCounters* __restrict__ rc) {
     constexpr int LCAP = BLOCK <= 64 ? 512 : (BLOCK <= 128 ? 1024 : (BLOCK <= 256 ? 2048 : 4096));
@@ -166,11 +168,12 @@ __global__ __launch_bounds__(BLOCK, 4) void propagate_kernel(const Job* __restri
         s_coef64[tid] = coef_table<double>()[tid];
     }
     uint32_t* __restrict__ plane = slots.planes + (size_t)slot * (size_t)slots.plane_cells;
-    const int64_t cap = slots.list_cap;
-    uint8_t* lb = slots.lists + (size_t)slot * (size_t)cap * (size_t)kSlotListBytesPerEntry;
-    uint2* const gW[2] = {(uint2*)lb, (uint2*)lb + cap};
-    Cont* const gC[2] = {(Cont*)(lb + 16 * cap), (Cont*)(lb + 16 * cap) + cap};
-    uint32_t* const gP[2] = {(uint32_t*)(lb + 64 * cap), (uint32_t*)(lb + 64 * cap) + cap};
+    const int64_t stride = slots.list_cap;   // entries allocated per list
+    const int64_t cap = slots.list_limit;    // entries used per list (<= stride)
+    uint8_t* lb = slots.lists + (size_t)slot * (size_t)stride * (size_t)kSlotListBytesPerEntry;
+    uint2* const gW[2] = {(uint2*)lb, (uint2*)lb + stride};
+    Cont* const gC[2] = {(Cont*)(lb + 16 * stride), (Cont*)(lb + 16 * stride) + stride};
+    uint32_t* const gP[2] = {(uint32_t*)(lb + 64 * stride), (uint32_t*)(lb + 64 * stride) + stride};
 
     for (;;) {
         if (tid == 0) {

@@ -93,12 +93,14 @@ struct Cont {
 constexpr int64_t kSlotListBytesPerEntry = 2 * 8 + 2 * 24 + 2 * 4;
 
 // Work slots: one per resident work group.  Each owns an arrival plane of
-// plane_cells labels, its lists and a tag.
+// plane_cells labels, its lists and a tag.  A launch uses list_limit entries
+// of each list; the buffers may hold more from an earlier, larger launch.
 struct Slots {
     uint32_t* planes;
     int64_t plane_cells;
     uint8_t* lists;
-    int64_t list_cap;
+    int64_t list_cap;     // entries allocated per list (layout stride)
+    int64_t list_limit;   // entries a launch may use (overflow beyond it)
     uint32_t* tags;
 };
 

@@ -205,3 +205,63 @@ def query_stream(n_queries: int, rate_per_s: float, seed: int, side_min: int = 1
     sides = np.rint(np.exp(rng.uniform(math.log(side_min), math.log(side_max), size=n_queries)))
     reps = rng.integers(1, reps_max + 1, size=n_queries)
     return [(float(t[i]), int(sides[i]), int(reps[i])) for i in range(n_queries)]
+
+
+@dataclass
+class Query:
+    """One served request: arrival time, its landscape crop and settings."""
+    qid: int
+    t: float          # arrival, seconds after the stream starts
+    side: int         # landscape side, cells
+    reps: int
+    row0: int         # top-left corner of the crop in the base landscape
+    col0: int
+    seed: int         # Philox key of the request (the query id)
+
+
+@dataclass
+class ServedStream:
+    """A Poisson stream of Monte-Carlo queries over crops of one base
+    landscape, sharing one set of weather scenarios."""
+    name: str
+    fuel: np.ndarray          # uint8 [base, base]
+    elev: np.ndarray          # int16 [base, base]
+    weather: np.ndarray       # float32 [S, P, 4]
+    queries: list
+    cell_m: int = 100
+    n_periods: int = 48
+    sigma: float = 0.15
+    rounding: int = 1
+    precision: int = 0
+
+    def crop(self, q: Query) -> tuple:
+        r, c, s = q.row0, q.col0, q.side
+        return (np.ascontiguousarray(self.fuel[r:r + s, c:c + s]),
+                np.ascontiguousarray(self.elev[r:r + s, c:c + s]))
+
+    @property
+    def cell_updates(self) -> int:
+        return sum(q.reps * q.side * q.side for q in self.queries) * self.n_periods
+
+
+def served_stream(n_queries: int = 1000, rate_per_s: float = 50.0, seed: int = 8,
+                  base_side: int = 4096, side_min: int = 128, side_max: int = 4096,
+                  reps_max: int = 256, n_scenarios: int = 100, n_periods: int = 48,
+                  land_seed: int = 12, wx_seed0: int = 6) -> ServedStream:
+    """Query stream of query_stream(); each query's landscape is the crop of
+    its side at a position drawn from a generator seeded by the query id, and
+    its Philox key is the query id.  Uniform-burnable ignitions, uniform
+    scenarios, lognormal ROS noise sigma 0.15, stochastic rounding."""
+    base = max(base_side, side_max)
+    qs = []
+    for i, (t, side, reps) in enumerate(query_stream(n_queries, rate_per_s, seed, side_min,
+                                                     side_max, reps_max)):
+        rng = _rng(1_000_003 * (seed + 1) + i)
+        r0 = int(rng.integers(0, base - side + 1))
+        c0 = int(rng.integers(0, base - side + 1))
+        qs.append(Query(i, t, side, reps, r0, c0, i))
+    return ServedStream(f"served-{n_queries}q-{rate_per_s:g}qps-{side_min}to{side_max}",
+                        fuel_grid(base, base, land_seed),
+                        elevation_grid(base, base, land_seed + 1000),
+                        weather_scenarios(n_scenarios, n_periods, wx_seed0), qs,
+                        n_periods=n_periods)

@@ -38,6 +38,42 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(_lib.WeatherRow) == 16
 
 
+_STRUCTS = {"c2f_sim_params": "SimParams", "c2f_outputs": "Outputs", "c2f_weather_row": "WeatherRow",
+            "c2f_run_stats": "RunStats", "c2f_ticket_info": "TicketInfo"}
+
+
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a
+    C compiler lays out from include/c2f.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "c2f.h"', "int main(void) {"]
+    for cname, pyname in _STRUCTS.items():
+        lines.append(f'printf("{pyname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(_lib, pyname)._fields_:
+            lines.append(f'printf("{pyname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            name, key, val = line.split()
+            got[(name, key)] = int(val)
+    for pyname in _STRUCTS.values():
+        cls = getattr(_lib, pyname)
+        assert got[(pyname, "size")] == ctypes.sizeof(cls), pyname
+        for fname, _ in cls._fields_:
+            assert got[(pyname, fname)] == getattr(cls, fname).offset, (pyname, fname)
+
+
 @pytest.mark.parametrize("fuel", range(1, 16))
 def test_device_fuel_table_equals_oracle_table(fuel):
     assert np.array_equal(fbp_coefficients(fuel), oracle.fuel_coefficients(fuel))
