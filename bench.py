@@ -109,7 +109,7 @@ def cpu_baseline(w, budget_s: float, procs: int) -> dict:
                 break
         dt = time.perf_counter() - t0
         what = (f"the full workload simulated {runs} times" if w.reps == 1
-                else f"{runs} of the {w.reps} replications")
+                else f"{runs} replications (cycling through the workload's {w.reps})")
         return {"value": runs * w.rows * w.cols * w.n_periods / dt, "unit": "cell-updates/s",
                 "cores": 1, "kind": "oracle",
                 "sample": f"{what} by the single-threaded FP64 oracle in {dt:.1f} s"}
@@ -126,8 +126,33 @@ def cpu_baseline(w, budget_s: float, procs: int) -> dict:
     dt = max(r[1] for r in res)
     return {"value": reps_done * w.rows * w.cols * w.n_periods / dt, "unit": "cell-updates/s",
             "cores": procs, "kind": "oracle",
-            "sample": (f"{reps_done} of the {w.reps} replications, sharded over {procs} "
-                       f"single-threaded FP64 oracle processes, in {dt:.1f} s")}
+            "sample": (f"{reps_done} replications (cycling through the workload's {w.reps}) "
+                       f"sharded over {procs} single-threaded FP64 oracle processes, in {dt:.1f} s")}
+
+
+def one_per_launch(sim, req, w, n: int, batched: dict, ms_batched: float) -> dict:
+    """Time the same replications one simulation per launch (reps=1 with
+    rep_offset r) and check each against the batched launch."""
+    import dataclasses
+
+    import torch
+    n = min(n, w.reps)
+    counts = None
+    same = True
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(n):
+        o = sim.simulate(dataclasses.replace(req, reps=1, rep_offset=r,
+                                             outputs=("burn_count", "burned_cells")))
+        same &= bool(o["burned_cells"][0].item() == batched["burned_cells"][r].item())
+        counts = o["burn_count"].clone() if counts is None else counts + o["burn_count"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) * 1e3
+    if n == w.reps:
+        same &= bool(torch.equal(counts, batched["burn_count"]))
+    ms_rep = dt / n
+    return {"reps_timed": n, "ms_per_rep": ms_rep, "est_ms_all_reps": ms_rep * w.reps,
+            "batched_speedup": ms_rep * w.reps / ms_batched, "identical_to_batched": same}
 
 
 def copy_calibration(args) -> None:
@@ -212,6 +237,9 @@ def main():
                     help="oracle worker processes for multi-replication workloads "
                          "(default: min(16, host CPUs))")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--per-launch", type=int, default=-1,
+                    help="also time this many replications one per launch (default: 64 for "
+                         "multi-replication workloads, 0 = off)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--queries", type=int, default=1000, help="served: queries in the stream")
     ap.add_argument("--rate", type=float, default=50.0, help="served: Poisson arrivals per second")
@@ -310,6 +338,10 @@ def main():
                      "kernel": "c2f::propagate_kernel", "kernel_ms": kernel_ms,
                      "alg_bytes_per_launch": alg_bytes},
     }
+    n_single = args.per_launch if args.per_launch >= 0 else (64 if w.reps > 1 else 0)
+    if n_single > 0 and w.reps > 1:
+        print("[bench] timing one replication per launch", file=sys.stderr, flush=True)
+        line["one_per_launch"] = one_per_launch(sim, req, w, n_single, out, ms)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         procs = args.cpu_procs or min(16, os.cpu_count() or 1)

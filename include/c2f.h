@@ -68,8 +68,10 @@ void c2f_destroy(c2f_ctx* ctx);
  * next call on the context. */
 const char* c2f_last_error(const c2f_ctx* ctx);
 
-/* Order all later work on `hip_stream` (a hipStream_t, e.g. torch's current
- * stream); NULL selects the context's own stream.  Default priority only. */
+/* Order all later synchronous work on `hip_stream` (a hipStream_t, e.g.
+ * torch's current stream); NULL selects the context's own stream, a
+ * blocking stream that is ordered with the legacy null stream.  Default
+ * priority only. */
 c2f_status c2f_set_stream(c2f_ctx* ctx, void* hip_stream);
 
 /* Upload a landscape (Section 3.5 (i)): fuel codes [rows*cols] (host) and

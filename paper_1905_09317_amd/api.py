@@ -233,6 +233,12 @@ class Simulator:
     def submit(self, req: Request) -> tuple[int, dict]:
         """Queue a request; returns (ticket, outputs that fill in when done)."""
         res, o = self._alloc_outputs(req)
+        if req.device_out:
+            # serving lanes run on their own streams: work of the caller's
+            # stream that may still use these (possibly reused) buffers
+            # must finish first
+            import torch
+            torch.cuda.current_stream(self._device).synchronize()
         p = req.params()
         t = ctypes.c_uint64()
         self._check(self._L.c2f_submit(self._ctx, ctypes.byref(p), ctypes.byref(o), ctypes.byref(t)))

@@ -109,6 +109,8 @@ struct Exec {
 
     void* staging = nullptr;          // device copy of host-bound outputs
     size_t staging_bytes = 0;
+    int2* item_slot = nullptr;        // {slot, tag} per item of a launch
+    int32_t item_slot_cap = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     c2f_run_stats last{};
@@ -285,9 +287,13 @@ void drop_graph(Exec& ex) {
     ex.graph_key.clear();
 }
 
-c2f_status exec_init(c2f_ctx* ctx, Exec& ex, bool round_up) {
-    ex.round_up = round_up;
-    HIP_TRY(ctx, hipStreamCreateWithFlags(&ex.own_stream, hipStreamNonBlocking));
+// The main executor's own stream is a blocking stream, ordered with the
+// legacy null stream both ways (callers such as torch's default stream see
+// library writes in order); serving lanes use non-blocking streams and
+// complete their requests before reporting them done.
+c2f_status exec_init(c2f_ctx* ctx, Exec& ex, bool lane) {
+    ex.round_up = lane;
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ex.own_stream, lane ? hipStreamNonBlocking : hipStreamDefault));
     ex.stream = ex.own_stream;
     HIP_TRY(ctx, hipEventCreate(&ex.ev0));
     HIP_TRY(ctx, hipEventCreate(&ex.ev1));
@@ -306,6 +312,9 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
     dev_free(ctx, ex.staging, ex.staging_bytes);
     dev_free(ctx, ex.d_jobs, (size_t)ex.d_jobs_cap * sizeof(Job));
+    dev_free(ctx, ex.item_slot, (size_t)ex.item_slot_cap * sizeof(int2));
+    ex.item_slot = nullptr;
+    ex.item_slot_cap = 0;
     ex.planes = nullptr;
     ex.n_slots = 0;
     ex.plane_cells = 0;
@@ -377,6 +386,7 @@ size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t
         g += (size_t)s.list_slots * s.list_cap * kSlotListBytesPerEntry -
              (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry;
     if (stage > ex.staging_bytes) g += stage - ex.staging_bytes;
+    if (n > ex.item_slot_cap) g += ((size_t)pow2_at_least(std::max(n, 64)) - (size_t)ex.item_slot_cap) * sizeof(int2);
     return g;
 }
 
@@ -434,6 +444,20 @@ c2f_status ensure_jobs(c2f_ctx* ctx, Exec& ex, int32_t n) {
         const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
         HIP_TRY(ctx, hipHostMalloc((void**)&ex.h_jobs, (size_t)cap * sizeof(Job), hipHostMallocDefault));
         ex.h_jobs_cap = cap;
+    }
+    return C2F_OK;
+}
+
+c2f_status ensure_item_slots(c2f_ctx* ctx, Exec& ex, int32_t n) {
+    if (n > ex.item_slot_cap) {
+        drop_graph(ex);
+        dev_free(ctx, ex.item_slot, (size_t)ex.item_slot_cap * sizeof(int2));
+        ex.item_slot = nullptr;
+        ex.item_slot_cap = 0;
+        const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
+        c2f_status st = dev_alloc(ctx, (void**)&ex.item_slot, (size_t)cap * sizeof(int2));
+        if (st != C2F_OK) return st;
+        ex.item_slot_cap = cap;
     }
     return C2F_OK;
 }
@@ -508,7 +532,9 @@ LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t
             lp.block = it->second.block;
             lp.cap = it->second.list_cap;
         } else {
-            lp.block = cells >= (1 << 22) && total_items <= 16 ? 1024 : 256;
+            // few replications on a large grid: wide groups (512 threads keep
+            // 2 waves per SIMD and all 256 VGPRs; 1024 would force 4 and spill)
+            lp.block = cells >= (1 << 22) && total_items <= 16 ? 512 : 256;
             lp.cap = default_list_cap(cells, total_items);
         }
         if (ctx->block_override) lp.block = ctx->block_override;
@@ -536,6 +562,8 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     LaunchPlan lp = plan_launch(ctx, max_cells, total, precision, grid_cap);
     c2f_status st = ensure_jobs(ctx, ex, (int32_t)idx.size());
     if (st != C2F_OK) return st;
+    bool dense = false;
+    for (int k : idx) dense |= plans[k].scar || plans[k].arr_minute || plans[k].arr_period;
 
     for (;;) {
         st = ensure_slots(ctx, ex, lp.grid, max_cells, lp.cap);
@@ -593,14 +621,21 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
         HIP_TRY(ctx, hipMemcpyAsync(ex.d_jobs, ex.h_jobs, idx.size() * sizeof(Job), hipMemcpyHostToDevice,
                                     ex.stream));
 
+        // dense outputs by a grid-wide kernel when no slot runs two items
+        const bool defer = dense && total <= lp.grid && total <= 65535;
+        if (defer) {
+            st = ensure_item_slots(ctx, ex, total);
+            if (st != C2F_OK) return st;
+        }
         const int64_t limit = std::min(lp.cap, ex.list_cap);
-        Slots sl{ex.planes, ex.plane_cells, ex.lists, ex.list_cap, limit, ex.tags};
+        Slots sl{ex.planes, ex.plane_cells, ex.lists, ex.list_cap, limit, ex.tags, defer ? ex.item_slot : nullptr};
         // key of the launch sequence for graph reuse
         std::vector<uint64_t> key = {(uint64_t)(uintptr_t)ex.d_jobs, idx.size(), (uint64_t)total,
                                      (uint64_t)lp.block, (uint64_t)lp.grid, (uint64_t)precision,
                                      (uint64_t)(uintptr_t)ex.planes, (uint64_t)(uintptr_t)ex.lists,
                                      (uint64_t)ex.list_cap, (uint64_t)limit, (uint64_t)ex.plane_cells,
-                                     (uint64_t)(uintptr_t)ex.stream};
+                                     (uint64_t)(uintptr_t)ex.stream, (uint64_t)defer,
+                                     (uint64_t)(uintptr_t)ex.item_slot};
         for (int k : idx) {
             key.push_back((uint64_t)(uintptr_t)plans[k].count);
             key.push_back((uint64_t)Ls[k]->ncells());
@@ -610,14 +645,21 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
         auto enqueue = [&]() -> hipError_t {
             hipError_t e = launch_fill_u32((uint32_t*)ex.rc, sizeof(RunCounters) / 4, 0u, ex.stream);
             if (e != hipSuccess) return e;
+            if (defer) {
+                e = launch_fill_u32((uint32_t*)ex.item_slot, (size_t)total * 2, 0xFFFFFFFFu, ex.stream);
+                if (e != hipSuccess) return e;
+            }
             for (int k : idx) {
                 if (plans[k].count) {
                     e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->ncells(), 0u, ex.stream);
                     if (e != hipSuccess) return e;
                 }
             }
-            return launch_propagate(precision, lp.block, lp.grid, ex.d_jobs, (int)idx.size(), total, sl, ex.rc,
-                                    ex.stream);
+            e = launch_propagate(precision, lp.block, lp.grid, ex.d_jobs, (int)idx.size(), total, sl, ex.rc,
+                                 ex.stream);
+            if (e != hipSuccess || !defer) return e;
+            return launch_dense_outputs(ex.d_jobs, (int)idx.size(), total, lp.grid, max_cells, sl, ex.rc,
+                                        ex.stream);
         };
         bool launched = false;
         if (use_graph && !ex.graph_unavailable) {

@@ -17,6 +17,7 @@ __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
 __device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
@@ -163,7 +164,7 @@ __device__ __forceinline__ double isf_curve(const CoefR<double>& k, double sfc, 
     return -log(t) * recip(k.b);
 }
 
-__device__ __noinline__ double slope_wind(const CoefR<double>* coef, int f, double sfc, double sfd,
+__device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, double sfc, double sfd,
                                           const double* row, const LandR<double>& L) {
     const double ff = row[0], isz = row[1];
     double isf;
@@ -180,6 +181,28 @@ __device__ __noinline__ double slope_wind(const CoefR<double>* coef, int f, doub
     return wse;
 }
 
+// The same in FP32 for the ordinary branch (WSE <= 40 km/h).  ln(1 - x) is
+// taken as log1p(-x), so a gentle slope (x close to the zero-slope value)
+// keeps full relative precision in ISF, and WSE = ln(ISF / ISZ) / 0.05039
+// then carries an absolute error of a few 1e-6 km/h.  Near and above the
+// 40 km/h branch point the caller switches to slope_wind in FP64.
+__device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float sfc, float g) {
+    const float x = sfc * g;
+    return -m_log1p(-(x > 0.99f ? 0.99f : x)) * recip(k.b);
+}
+
+__device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, float sfc, float sfd,
+                                              const float* row, const LandR<float>& L) {
+    float isf;
+    if (f == kM1 || f == kM2) {
+        isf = L.pc_w * isf_curve32(coef[kC2], sfc, row[kRowG + kC2]) +
+              (1.0f - L.pc_w) * isf_curve32(coef[kD1], sfd, row[kRowG + kD1]);
+    } else {
+        isf = isf_curve32(coef[f], sfc, row[kRowG + f]);
+    }
+    return m_log(isf * recip(row[1])) * (1.0f / 0.05039f);
+}
+
 // Head and back rates, length-to-breadth ratio and the effective wind
 // vector (east, north components; its direction is the head direction).
 template <typename R>
@@ -187,21 +210,27 @@ struct CellRates {
     R h, b, lb, lbm1, wx, wy, wsv;   // lbm1 = LB - 1, kept separately for accuracy
 };
 
-// Everything is evaluated in R except the slope-equivalent wind, which is
-// FP64 in both modes: inverting the rate curve near its asymptote (the
+// Everything is evaluated in R.  In FP32 the slope-equivalent wind switches
+// to FP64 from 39 km/h up: inverting the rate curve near its asymptote (the
 // WSE > 40 branch) turns a relative error of 1e-7 in ISF into ~1e-4 in WSE.
 // row64 is the FP64 weather row of the same (scenario, period).
 template <typename R>
-__device__ __noinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64,
+__device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64,
                                                 const CellRec& rec, const R* row, const double* row64,
                                                 const LandR<R>& L, const LandR<double>& L64) {
     const int f = rec_fuel(rec.info), gx = rec_gx(rec.grad), gn = rec_gn(rec.grad);
     R wx = row[2], wy = row[3];
     if ((gx | gn) != 0) {
-        const double ig = recip(sqrt((double)gx * (double)gx + (double)gn * (double)gn));
-        const double wse = slope_wind(coef64, f, rec.sfc, rec.sfd, row64, L64);
-        wx += (R)(wse * ((double)gx * ig));                                // along the upslope unit vector
-        wy += (R)(wse * ((double)gn * ig));
+        R wse = (R)0;
+        bool need64 = true;
+        if constexpr (sizeof(R) == 4) {
+            wse = slope_wind32(coef, f, (float)rec.sfc, (float)rec.sfd, row, L);
+            need64 = !(wse < 39.0f);
+        }
+        if (need64) wse = (R)slope_wind(coef64, f, rec.sfc, rec.sfd, row64, L64);
+        const R ig = recip(m_sqrt((R)gx * (R)gx + (R)gn * (R)gn));
+        wx += wse * ((R)gx * ig);                                          // along the upslope unit vector
+        wy += wse * ((R)gn * ig);
     }
     const R wsv = m_sqrt(wx * wx + wy * wy);
     const R fw = (wsv <= (R)40) ? m_exp((R)0.05039 * wsv)

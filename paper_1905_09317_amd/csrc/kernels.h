@@ -28,4 +28,10 @@ hipError_t launch_propagate(int precision, int block, int grid, const Job* jobs,
                             const Slots& slots, RunCounters* rc, hipStream_t s);
 int propagate_blocks_per_cu(int precision, int block);
 
+// Dense per-replication outputs of a launch whose items each kept a slot
+// (slots.item_slot filled by the propagation, cleared to -1 before it);
+// total <= 65535; nothing is written if the launch overflowed.
+hipError_t launch_dense_outputs(const Job* jobs, int n_jobs, int total, int n_slots, int64_t max_cells,
+                                const Slots& slots, const RunCounters* rc, hipStream_t s);
+
 }  // namespace c2f

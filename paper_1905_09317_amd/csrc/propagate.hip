@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 #include "types.h"
@@ -486,7 +488,9 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         atomicAdd(&s_cnt[kCntImprovements], (unsigned long long)c_impr);
         if (tid == 0) s_cnt[kCntRounds] = (unsigned long long)c_rounds;
         atomicMax(&s_cnt[kCntMaxList], (unsigned long long)max_list);
-        if (job.scar || job.arr_minute || job.arr_period) {
+        if (slots.item_slot) {
+            if (tid == 0) slots.item_slot[item] = make_int2(slot, (int)tag);
+        } else if (job.scar || job.arr_minute || job.arr_period) {
             __syncthreads();
             const size_t n = (size_t)job.rows * cols;
             const size_t o = (size_t)lr * n;
@@ -509,6 +513,48 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         }
         __syncthreads();
     }
+}
+
+// Dense per-replication outputs from the final arrival planes, one thread
+// per (item, cell): used when every item of the launch kept its own slot.
+__global__ __launch_bounds__(256) void dense_outputs_kernel(const Job* __restrict__ jobs, int n_jobs,
+                                                            int total_items, int n_slots, Slots slots,
+                                                            const RunCounters* __restrict__ rc) {
+    const int item = blockIdx.y;
+    if (item >= total_items || rc->overflow) return;   // an overflowed launch is repeated
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item_base <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const Job& job = jobs[lo];
+    if (!(job.scar || job.arr_minute || job.arr_period)) return;
+    const int2 st = slots.item_slot[item];
+    if (st.x < 0 || st.x >= n_slots) return;   // item not run (cleared to -1 before the launch)
+    const uint32_t tag = (uint32_t)st.y;
+    const uint32_t* __restrict__ plane = slots.planes + (size_t)st.x * (size_t)slots.plane_cells;
+    const size_t n = (size_t)job.rows * (size_t)job.cols;
+    const size_t o = (size_t)(item - job.item_base) * n;
+    const int P = job.period_min;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t v = plane[i];
+        const bool on = (v >> kMinuteBits) == tag && (v & kMinuteMask) != kPendingMinute;
+        const int32_t t = on ? (int32_t)(v & kMinuteMask) : -1;
+        if (job.scar) job.scar[o + i] = (uint8_t)on;
+        if (job.arr_minute) job.arr_minute[o + i] = t;
+        if (job.arr_period) job.arr_period[o + i] = !on ? -1 : (t == 0 ? 0 : (t - 1) / P);
+    }
+}
+
+hipError_t launch_dense_outputs(const Job* jobs, int n_jobs, int total, int n_slots, int64_t max_cells,
+                                const Slots& slots, const RunCounters* rc, hipStream_t s) {
+    if (total <= 0 || total > 65535 || !slots.item_slot) return hipErrorInvalidValue;
+    const int64_t want = (max_cells + 255) / 256;
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096 / std::min(total, 16)));
+    hipLaunchKernelGGL(dense_outputs_kernel, dim3(gx, total), dim3(256), 0, s, jobs, n_jobs, total, n_slots, slots,
+                       rc);
+    return hipGetLastError();
 }
 
 template <typename R>

@@ -102,6 +102,11 @@ struct Slots {
     int64_t list_cap;     // entries allocated per list (layout stride)
     int64_t list_limit;   // entries a launch may use (overflow beyond it)
     uint32_t* tags;
+    // When every item of a launch has a slot of its own, the per-rep dense
+    // outputs (scar, arrival minute and period) are written after the
+    // propagation by a grid-wide kernel: item_slot[item] = {slot, tag}.
+    // NULL: each work group writes them at the end of its replication.
+    int2* item_slot;
 };
 
 enum Counter {

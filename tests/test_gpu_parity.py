@@ -264,6 +264,32 @@ def test_device_outputs(sim):
     sim.unset_weather(x)
 
 
+def test_device_outputs_accumulate_on_default_stream(sim):
+    """Device outputs of consecutive calls, summed by torch on its default
+    stream without synchronising: the library's writes stay ordered with the
+    pending additions that still read reused buffers."""
+    import dataclasses
+
+    import torch
+    _say("device outputs, default stream")
+    w = inputs.batched_monte_carlo(side=1024, reps=16, n_scenarios=2, n_periods=8)
+    land = sim.load_landscape(w.fuel, w.elev)
+    x = sim.set_weather(w.weather)
+    req = Request(landscape=land, weather=x, device_out=True,
+                  outputs=("burn_count", "burned_cells"), **request_kwargs(w))
+    whole = sim.simulate(req)
+    counts = None
+    for r in range(w.reps):
+        o = sim.simulate(dataclasses.replace(req, reps=1, rep_offset=r))
+        counts = o["burn_count"].clone() if counts is None else counts + o["burn_count"]
+    torch.cuda.synchronize()
+    assert torch.equal(counts, whole["burn_count"])
+    assert int(counts.sum().item()) == int(whole["burned_cells"].sum().item())
+    sim.set_stream(None)
+    sim.unload_landscape(land)
+    sim.unset_weather(x)
+
+
 # ------------------------------------------------------- medium workloads
 
 def test_single_fire_512_fp64(sim):
