@@ -28,10 +28,32 @@ sys.path.insert(0, ROOT)
 #     + 16 B work-list entry read + 16 B entry write           = 37 B
 #   arrival candidate offered to a neighbour: 1 B fuel + 8 B label RMW = 9 B
 #   ignition: 16 B list append + 8 B burn-count RMW              = 24 B
-#   per cell of the grid: 4 B burn-count initialisation
-#   per cell per rep of dense outputs: 4 B label read + 1 B scar + 4 B period
-B_EVAL, B_CAND, B_IGN, B_CELL, B_DENSE = 37, 9, 24, 4, 9
+#   per cell per rep of dense outputs: 4 B label read + 1 B scar + 4 B period,
+#     counted only when the propagation kernel writes them itself (a launch
+#     where every replication keeps its slot leaves them to a grid-wide kernel)
+# The burn-count initialisation (4 B per cell) is a separate fill kernel.
+B_EVAL, B_CAND, B_IGN, B_DENSE = 37, 9, 24, 9
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the propagation kernel measured with rocprofv3
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a plain 256 MiB
+# copy), valid for the kernel sources whose digest is given; reported as
+# roofline.traffic only while the sources are unchanged.
+KERNEL_SOURCES = ("propagate.hip", "device.h", "types.h", "fuel_table.h")
+TRAFFIC = {
+    "single-fire-2048x2048-48h": ("b178d75f4888be5f", 10_055_413),
+    "batched-mc-1024x1024-2048reps": ("b178d75f4888be5f", 39_217_674_059),
+    "large-8192x8192-64reps-72h": ("b178d75f4888be5f", 796_582_082),
+}
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_09317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def make_workload(name: str):
@@ -301,9 +323,12 @@ def main():
 
     st = stats[-1]
     n = w.rows * w.cols
-    dense = w.reps * n * B_DENSE if "scar" in dense_outputs(w) else 0
-    alg_bytes = (B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"]
-                 + B_CELL * n + dense)
+    deferred = w.reps <= st["grid_blocks"]
+    dense = w.reps * n * B_DENSE if ("scar" in dense_outputs(w) and not deferred) else 0
+    alg_bytes = B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"] + dense
+    traffic = None
+    if w.name in TRAFFIC and TRAFFIC[w.name][0] == kernel_digest():
+        traffic = TRAFFIC[w.name][1]
     kernel_ms = sum(kms) / len(kms)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     burned = int(out["burned_cells"].sum().item())
@@ -334,7 +359,7 @@ def main():
         "counters": {k: st[k] for k in ("ignitions", "entries", "continuations", "rounds",
                                         "rate_evals", "candidates", "improvements", "relaunches")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "c2f::propagate_kernel", "kernel_ms": kernel_ms,
                      "alg_bytes_per_launch": alg_bytes},
     }
