@@ -46,10 +46,13 @@ def _load():
         L.oracle_axis_ros.restype = None
         L.oracle_eval_ros.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, P, i32, i32, i32,
                                       u64, f64, i32, P, P, P, P, P, P, P, P]
+        L.oracle_eval_ros_cells.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, P, i32, i32,
+                                            i32, u64, f64, i32, i64, P, P, P, P, P, P, P, P, P]
         L.oracle_simulate.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
                                       i32, i32, i32, u64, f64, f64, i32, i32, i32, i32, i32,
                                       i32, P, P, P, P, P, P, P, P, P, P]
-        for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_simulate"):
+        for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_eval_ros_cells",
+                   "oracle_simulate"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -116,20 +119,24 @@ def _land(fuel, elev, weather):
 
 
 def eval_ros(fuel, elev, weather, *, cell_m=100, scenario=0, period=0, rep=0, seed=0, sigma=0.0,
-             rounding=0, pc=50.0, curing=80.0) -> dict:
+             rounding=0, pc=50.0, curing=80.0, cells=None) -> dict:
+    """Per-cell rate field; with `cells` (grid indices) only those cells,
+    outputs indexed by position in `cells`."""
     f, e, w = _land(fuel, elev, weather)
     rows, cols = f.shape
-    n = rows * cols
+    sel = None if cells is None else np.ascontiguousarray(cells, dtype=np.int32)
+    n = rows * cols if sel is None else sel.size
     out = {k: np.zeros(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz")}
     out["x8"] = np.zeros((n, 8), np.float64)
     out["xu8"] = np.zeros((n, 8), np.float64)
     out["q8"] = np.zeros((n, 8), np.int32)
-    rc = _load().oracle_eval_ros(rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc),
-                                 float(curing), w.shape[0], w.shape[1], _ptr(w), int(scenario),
-                                 int(period), int(rep), int(seed) & (2**64 - 1), float(sigma),
-                                 int(rounding), _ptr(out["hros"]), _ptr(out["bros"]),
-                                 _ptr(out["fros"]), _ptr(out["lb"]), _ptr(out["raz"]),
-                                 _ptr(out["x8"]), _ptr(out["xu8"]), _ptr(out["q8"]))
+    rc = _load().oracle_eval_ros_cells(rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc),
+                                       float(curing), w.shape[0], w.shape[1], _ptr(w), int(scenario),
+                                       int(period), int(rep), int(seed) & (2**64 - 1), float(sigma),
+                                       int(rounding), -1 if sel is None else int(sel.size),
+                                       _ptr(sel), _ptr(out["hros"]), _ptr(out["bros"]),
+                                       _ptr(out["fros"]), _ptr(out["lb"]), _ptr(out["raz"]),
+                                       _ptr(out["x8"]), _ptr(out["xu8"]), _ptr(out["q8"]))
     if rc != 0:
         raise ValueError("oracle_eval_ros: bad input")
     return out

@@ -393,28 +393,44 @@ int oracle_eval_ros(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
                     int32_t rounding, double* hros, double* bros, double* fros, double* lb,
                     double* raz, double* x8, double* xu8, int32_t* q8) {
+    return oracle_eval_ros_cells(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
+                                 weather, scenario, period, rep, seed, sigma, rounding, -1, NULL, hros, bros,
+                                 fros, lb, raz, x8, xu8, q8);
+}
+
+int oracle_eval_ros_cells(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
+                          const int16_t* elev, double pc_pct, double curing_pct,
+                          int32_t n_scen, int32_t n_wperiods, const float* weather,
+                          int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
+                          int32_t rounding, int64_t n_cells, const int32_t* cells, double* hros,
+                          double* bros, double* fros, double* lb, double* raz, double* x8, double* xu8,
+                          int32_t* q8) {
     if (check_land(rows, cols, cell_m, fuel, pc_pct, curing_pct, n_scen, n_wperiods, weather)) return -1;
     if (scenario < 0 || scenario >= n_scen || period < 0 || period >= n_wperiods || rep < 0) return -1;
     if (!(sigma >= 0.0) || (rounding != 0 && rounding != 1)) return -1;
     land_t L;
     init_land(&L, rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods, weather);
-    int64_t n = (int64_t)rows * cols;
-    for (int64_t i = 0; i < n; ++i) {
+    const int64_t n = cells ? n_cells : (int64_t)rows * cols;
+    for (int64_t k = 0; k < n; ++k) {
+        if (cells && (cells[k] < 0 || (int64_t)cells[k] >= (int64_t)rows * cols)) return -1;
+    }
+    for (int64_t o = 0; o < n; ++o) {
+        const int64_t i = cells ? cells[o] : o;   /* grid cell; outputs are indexed by o */
         cellros_t c;
         if (fuel[i] == 0) {
             memset(&c, 0, sizeof c);
         } else {
             cell_ros(&L, (int)i, scenario, period, rep, seed, sigma, rounding, &c);
         }
-        if (hros) hros[i] = c.h;
-        if (bros) bros[i] = c.b;
-        if (fros) fros[i] = c.f;
-        if (lb) lb[i] = c.lb;
-        if (raz) raz[i] = c.raz;
+        if (hros) hros[o] = c.h;
+        if (bros) bros[o] = c.b;
+        if (fros) fros[o] = c.f;
+        if (lb) lb[o] = c.lb;
+        if (raz) raz[o] = c.raz;
         for (int k = 0; k < 8; ++k) {
-            if (x8) x8[i * 8 + k] = c.x[k];
-            if (xu8) xu8[i * 8 + k] = c.xu[k];
-            if (q8) q8[i * 8 + k] = c.q[k];
+            if (x8) x8[o * 8 + k] = c.x[k];
+            if (xu8) xu8[o * 8 + k] = c.xu[k];
+            if (q8) q8[o * 8 + k] = c.q[k];
         }
     }
     return 0;

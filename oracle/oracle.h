@@ -51,6 +51,17 @@ int oracle_eval_ros(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     int32_t rounding, double* hros, double* bros, double* fros, double* lb,
                     double* raz, double* x8, double* xu8, int32_t* q8);
 
+/* The same for the listed grid cells only: outputs are indexed by the
+ * position in `cells` ([n_cells], [n_cells][8]); cells == NULL means every
+ * cell in row-major order. */
+int oracle_eval_ros_cells(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
+                          const int16_t* elev, double pc_pct, double curing_pct,
+                          int32_t n_scen, int32_t n_wperiods, const float* weather,
+                          int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
+                          int32_t rounding, int64_t n_cells, const int32_t* cells, double* hros,
+                          double* bros, double* fros, double* lb, double* raz, double* x8, double* xu8,
+                          int32_t* q8);
+
 /* Monte-Carlo fire simulation.  Replication r uses global index
  * rep_offset + r in every random draw.  Outputs may be NULL.
  * scar/arrival_* are [reps][rows*cols]; burn_count [rows*cols] is

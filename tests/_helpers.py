@@ -62,27 +62,42 @@ def boundary_case(xu: np.ndarray, x: np.ndarray, tol_rel: float) -> np.ndarray:
 
 
 def fp32_overrides(sim, land, wx, fuel, elev, weather, *, reps, n_periods, seed, sigma, rounding,
-                   scenarios, cell_m=100, pc=50.0, curing=80.0, tol_rel=2e-5):
+                   scenarios, cell_m=100, pc=50.0, curing=80.0, tol_rel=2e-5, cells=None):
     """Audit FP32 integer rates against the FP64 oracle for every (rep, period)
-    and return (override keys, q) for the cells where they differ; every
-    difference must be a boundary case of the oracle's value."""
+    (on `cells` only, if given) and return (override keys, q) for the cells
+    where they differ; every difference must be a boundary case of the
+    oracle's value."""
     keys, qs, n_checked = [], [], 0
+    sel = None if cells is None else np.asarray(cells, np.int64)
     for r in range(reps):
         for p in range(n_periods):
             g = sim.eval_ros(land, wx, scenario=int(scenarios[r]), period=p, rep=r, seed=seed,
                              sigma=sigma, rounding=rounding, precision=1)
             o = oracle.eval_ros(fuel, elev, weather, cell_m=cell_m, scenario=int(scenarios[r]),
                                 period=p, rep=r, seed=seed, sigma=np.float32(sigma).item(),
-                                rounding=rounding, pc=pc, curing=curing)
-            diff = np.any(g["q8"] != o["q8"], axis=1)
-            n_checked += g["q8"].size
+                                rounding=rounding, pc=pc, curing=curing,
+                                cells=None if sel is None else sel.astype(np.int32))
+            gq = g["q8"] if sel is None else g["q8"][sel]
+            diff = np.any(gq != o["q8"], axis=1)
+            n_checked += gq.size
             if diff.any():
-                cells = np.nonzero(diff)[0]
-                ok = boundary_case(o["xu8"][cells], o["x8"][cells], tol_rel) | (g["q8"][cells] == o["q8"][cells])
-                assert ok.all(), f"rep {r} period {p}: non-boundary integer-rate mismatch at cells {cells[~ok.all(axis=1)][:5]}"
-                for c in cells:
-                    keys.append((r, p, int(c)))
-                    qs.append(g["q8"][c])
+                pos = np.nonzero(diff)[0]
+                ok = boundary_case(o["xu8"][pos], o["x8"][pos], tol_rel) | (gq[pos] == o["q8"][pos])
+                assert ok.all(), f"rep {r} period {p}: non-boundary integer-rate mismatch at {pos[~ok.all(axis=1)][:5]}"
+                for i in pos:
+                    c = int(i) if sel is None else int(sel[i])
+                    keys.append((r, p, c))
+                    qs.append(gq[i])
     k = np.array(keys, np.int32).reshape(-1, 3)
     q = np.array(qs, np.int32).reshape(-1, 8)
     return k, q, n_checked
+
+
+def dilate(mask2d: np.ndarray, steps: int = 1) -> np.ndarray:
+    """8-neighbour dilation of a boolean grid."""
+    m = mask2d.copy()
+    for _ in range(steps):
+        p = np.pad(m, 1)
+        m = (p[:-2, :-2] | p[:-2, 1:-1] | p[:-2, 2:] | p[1:-1, :-2] | p[1:-1, 1:-1] | p[1:-1, 2:]
+             | p[2:, :-2] | p[2:, 1:-1] | p[2:, 2:])
+    return m

@@ -1,0 +1,106 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration bench.py times: the whole single fire against the oracle, and
+sampled replications of the batched and large workloads (the oracle runs one
+replication at a time) plus properties that hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1905_09317_amd import Request, Simulator, inputs
+
+from _helpers import assert_same_outputs, dilate, fp32_overrides, oracle_kwargs, oracle_run, request_kwargs
+
+pytestmark = pytest.mark.gpu
+
+SINGLE_OUTS = ("scar", "arrival_period", "burn_count", "burned_cells")
+MC_OUTS = ("burn_count", "burned_cells")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = Simulator(0)
+    yield s
+    s.close()
+
+
+def _run(sim, w, outputs, **over):
+    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    g = sim.simulate(Request(landscape=land, weather=wx, outputs=outputs, **request_kwargs(w, **over)))
+    return land, wx, g
+
+
+def test_single_fire_2048_fp64_full():
+    w = inputs.single_large_fire(side=2048, n_periods=48, precision=0)
+    with Simulator(0) as sim:
+        _say(f"[fullsize] {w.name} fp64")
+        _, _, g = _run(sim, w, SINGLE_OUTS)
+        st = sim.stats()
+    assert st["grid_blocks"] == 1 and st["block_threads"] == 512
+    ref = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w))
+    assert_same_outputs(g, ref, SINGLE_OUTS, where="single fire fp64")
+    assert int(g["burned_cells"][0]) > 10000
+
+
+def test_single_fire_2048_fp32_full_with_audited_rates():
+    """The bench's single-fire workload (FP32 rates).  Integer rates are
+    audited on every cell that burns in either run and its neighbours, for
+    every period; audited boundary cases are replayed into the oracle."""
+    w = inputs.single_large_fire(side=2048, n_periods=48, precision=1)
+    with Simulator(0) as sim:
+        _say(f"[fullsize] {w.name} fp32")
+        land, wx, g = _run(sim, w, SINGLE_OUTS)
+        ref0 = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w))
+        burnt = (np.asarray(g["scar"][0]) | ref0["scar"][0]).reshape(w.rows, w.cols).astype(bool)
+        cells = np.nonzero(dilate(burnt, 1).ravel())[0]
+        _say(f"[fullsize] auditing {cells.size} cells x {w.n_periods} periods")
+        keys, qs, n = fp32_overrides(sim, land, wx, w.fuel, w.elev, w.weather, reps=1,
+                                     n_periods=w.n_periods, seed=w.seed, sigma=w.sigma,
+                                     rounding=w.rounding, scenarios=[0], cells=cells)
+    _say(f"[fullsize] {len(keys)} boundary cases in {n} audited integer rates")
+    ref = oracle_run(w.fuel, w.elev, w.weather, overrides=(keys, qs), **oracle_kwargs(w))
+    assert_same_outputs(g, ref, SINGLE_OUTS, where="single fire fp32")
+
+
+def _sampled_mc(sim, w, sample):
+    _, _, g = _run(sim, w, MC_OUTS)
+    burned = np.asarray(g["burned_cells"])
+    counts = np.asarray(g["burn_count"]).view(np.uint32)
+    # properties at full size
+    assert int(counts.sum(dtype=np.int64)) == int(burned.sum())
+    assert int(counts.max()) <= w.reps
+    assert (burned >= 1).all()          # every replication ignites a burnable cell
+    for r in sample:
+        _say(f"[fullsize] {w.name}: oracle replication {r}")
+        ref = oracle_run(w.fuel, w.elev, w.weather, want_rep_outputs=False,
+                         **oracle_kwargs(w, reps=1, rep_offset=r))
+        assert int(burned[r]) == int(ref["burned_cells"][0]), f"replication {r}"
+    return g
+
+
+def test_batched_mc_1024_2048reps_sampled(sim):
+    w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48)
+    g = _sampled_mc(sim, w, (0, 1, 777, 1500, 2047))
+    st = sim.stats()
+    assert st["grid_blocks"] == 512 and st["relaunches"] == 0
+    # the burn-count map of a replication range equals the oracle's
+    ref = oracle_run(w.fuel, w.elev, w.weather, want_rep_outputs=False,
+                     **oracle_kwargs(w, reps=8, rep_offset=2040))
+    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m)
+    wx = sim.set_weather(w.weather)
+    part = sim.simulate(Request(landscape=land, weather=wx, outputs=MC_OUTS,
+                                **request_kwargs(w, reps=8, rep_offset=2040)))
+    assert_same_outputs(part, ref, MC_OUTS, where="reps 2040..2047")
+    assert np.array_equal(part["burned_cells"], np.asarray(g["burned_cells"])[2040:])
+
+
+def test_large_8192_64reps_sampled(sim):
+    w = inputs.large_landscape(side=8192, reps=64, n_periods=72)
+    _sampled_mc(sim, w, (0, 33, 63))
+    assert sim.stats()["grid_blocks"] == 64

@@ -213,3 +213,18 @@ def test_slope_field_through_eval_ros():
     assert r["raz"][centre] == pytest.approx(az, abs=1e-9)
     sf = math.exp(3.533 * (gs / 100.0) ** 1.2)
     assert r["hros"][centre] == pytest.approx(sf * flat["hros"][centre], rel=1e-11)
+
+
+def test_eval_ros_cell_subset_equals_full_grid():
+    """Selecting cells only changes which cells are evaluated, not the values."""
+    from paper_1905_09317_amd import inputs
+    w = inputs.batched_monte_carlo(side=48, reps=2, n_scenarios=3, n_periods=4)
+    full = oracle.eval_ros(w.fuel, w.elev, w.weather, scenario=2, period=3, rep=1, seed=9, sigma=0.2,
+                           rounding=1)
+    cells = np.array([0, 47, 48 * 48 - 1, 1000, 1000, 5], np.int32)
+    sub = oracle.eval_ros(w.fuel, w.elev, w.weather, scenario=2, period=3, rep=1, seed=9, sigma=0.2,
+                          rounding=1, cells=cells)
+    for k in full:
+        assert np.array_equal(full[k][cells], sub[k]), k
+    with pytest.raises(ValueError):
+        oracle.eval_ros(w.fuel, w.elev, w.weather, cells=np.array([48 * 48], np.int32))
