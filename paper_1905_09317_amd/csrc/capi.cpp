@@ -532,9 +532,10 @@ LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t
             lp.block = it->second.block;
             lp.cap = it->second.list_cap;
         } else {
-            // few replications on a large grid: wide groups (512 threads keep
-            // 2 waves per SIMD and all 256 VGPRs; 1024 would force 4 and spill)
-            lp.block = cells >= (1 << 22) && total_items <= 16 ? 512 : 256;
+            // few replications on a large grid: wide groups.  The FP64
+            // kernel keeps 512 threads (2 waves per SIMD, 256 VGPRs); at 1024
+            // it would be held to 128 VGPRs and spill.
+            lp.block = cells >= (1 << 22) && total_items <= 16 ? (precision == 1 ? 1024 : 512) : 256;
             lp.cap = default_list_cap(cells, total_items);
         }
         if (ctx->block_override) lp.block = ctx->block_override;

@@ -19,13 +19,17 @@
 //   - cells whose axes were still travelling at the end of p-1
 //     (continuations, with the metres left on each axis) are advanced
 //     through p;
-//   - label-correcting rounds: each cell that received a smaller arrival
-//     in p is advanced from that minute to the end of p.
+//   - label correcting: each cell that received a smaller arrival in p is
+//     advanced from that minute to the end of p.
 // Advancing a cell through a period costs one FBP evaluation; axes that
 // reach their neighbour inside p offer that minute with atomicMin on the
-// neighbour's 32-bit label, the rest become a continuation for p+1.  Round
-// lists live in LDS (spilling to the slot's global lists), appended with a
-// wave ballot and prefix count and one LDS atomic per wave.
+// neighbour's 32-bit label, the rest become a continuation for p+1.
+// Improved cells go to the period's work queue (LDS, spilling to the slot's
+// global list): each wave reserves a range with one LDS atomic, writes its
+// entries and commits the range in reservation order; waves take committed
+// chunks of up to 64 entries as soon as they are free, so no wave waits for
+// the others between hops.  The period ends when no wave holds a chunk and
+// every reserved entry has been taken.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -154,8 +158,13 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                                                           int total_items, Slots slots,
                                                           RunCounters* __restrict__ rc) {
     constexpr int LCAP = BLOCK <= 64 ? 512 : (BLOCK <= 128 ? 1024 : (BLOCK <= 256 ? 2048 : 4096));
-    __shared__ uint2 s_W[2][LCAP];
-    __shared__ int s_nW[2], s_nC[2], s_nP[2];
+    constexpr int LQ = 2 * LCAP;   // LDS part of the period queue
+    __shared__ uint2 s_Q[LQ];
+    __shared__ int s_res, s_commit;   // queue entries reserved, committed (in order)
+    // queue entries taken (high 32 bits) and waves holding a chunk (low 32),
+    // one word so that taking a chunk and becoming a holder is one step
+    __shared__ unsigned long long s_hb;
+    __shared__ int s_nC[2], s_nP[2];
     __shared__ int s_item, s_flag;
     __shared__ uint32_t s_tag;
     __shared__ int s_scen, s_ign;
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     const int64_t stride = slots.list_cap;   // entries allocated per list
     const int64_t cap = slots.list_limit;    // entries used per list (<= stride)
     uint8_t* lb = slots.lists + (size_t)slot * (size_t)stride * (size_t)kSlotListBytesPerEntry;
-    uint2* const gW[2] = {(uint2*)lb, (uint2*)lb + stride};
+    uint2* const gQ = (uint2*)lb;        // global part of the period queue: 2 x cap entries
     Cont* const gC[2] = {(Cont*)(lb + 16 * stride), (Cont*)(lb + 16 * stride) + stride};
     uint32_t* const gP[2] = {(uint32_t*)(lb + 64 * stride), (uint32_t*)(lb + 64 * stride) + stride};
 
@@ -210,7 +219,9 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         // ------------------------------------------- replication set-up
         if (tid == 0) {
             s_tag = slots.tags[slot];   // previous tag; refilled below if exhausted
-            s_nW[0] = s_nW[1] = s_nC[0] = s_nC[1] = s_nP[0] = s_nP[1] = 0;
+            s_res = s_commit = 0;
+            s_hb = 0ull;
+            s_nC[0] = s_nC[1] = s_nP[0] = s_nP[1] = 0;
             s_flag = 0;
             for (int k = 0; k < kNumCounters; ++k) s_cnt[k] = 0;
             int scen = job.scen_fixed;
@@ -248,8 +259,8 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             if (ign >= 0 && rec_fuel(cells[ign].info) != 0) {
                 const uint32_t v = tag << kMinuteBits;          // minute 0
                 plane[ign] = v;
-                s_W[0][0] = make_uint2((uint32_t)ign, v);
-                s_nW[0] = 1;
+                s_Q[0] = make_uint2((uint32_t)ign, v);
+                s_res = s_commit = 1;
                 s_cnt[kCntIgnitions] = 1;
                 if (job.count) atomicAdd(&job.count[ign], 1u);
             }
@@ -271,7 +282,35 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
 
         uint32_t c_entries = 0, c_conts = 0, c_evals = 0, c_cand = 0, c_impr = 0, c_ign = 0, c_rounds = 0;
         int max_list = 0;
-        int wc = 0, cc = 0, pc = 0;   // which buffer of each list pair is current
+        int cc = 0, pc = 0;   // which buffer of each list pair is current
+        const int64_t qcap = (int64_t)LQ + 2 * cap;   // queue entries per period
+
+        // Append one entry per lane where `pred` holds: one reservation per
+        // wave, entries written, then the range committed in reservation
+        // order (earlier reservations never wait on later ones).  Called in
+        // wave-uniform control flow.
+        auto q_commit = [&](int wbase, int wtot) __attribute__((always_inline)) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (__lane_id() == 0) {
+                while (__hip_atomic_load(&s_commit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != wbase)
+                    __builtin_amdgcn_s_sleep(1);
+                __hip_atomic_store(&s_commit, wbase + wtot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        };
+        auto q_put = [&](int idx, uint2 val) __attribute__((always_inline)) {
+            if (idx < LQ) s_Q[idx] = val;
+            else if ((int64_t)(idx - LQ) < 2 * cap) gQ[idx - LQ] = val;
+            else s_flag = 1;
+        };
+        auto q_append1 = [&](bool pred, uint2 val) __attribute__((always_inline)) {
+            const uint64_t m = __ballot(pred);
+            if (m == 0) return;
+            int wbase = 0;
+            if (__lane_id() == 0) wbase = atomicAdd(&s_res, (int)__popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (pred) q_put(wbase + wave_rank(m), val);
+            q_commit(wbase, (int)__popcll(m));
+        };
 
         for (int p = 0; p < job.n_periods; ++p) {
             const int32_t s = p * P + 1;   // first minute of period p
@@ -305,171 +344,225 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                     }
                     c_impr += improved;
                     c_ign += first;
-                    append_w(improved, make_uint2(j, v), s_W[wc], LCAP, gW[wc], cap, &s_nW[wc], &s_flag);
+                    q_append1(improved, make_uint2(j, v));
                     append_g(act && !ok, j, gP[pc ^ 1], cap, &s_nP[pc ^ 1], &s_flag);
                 }
             }
-            // Pass 0 advances the continuations of p-1 from the start of p;
-            // passes 1, 2, ... are label-correcting rounds over the cells that
-            // received a smaller arrival inside p, advanced from that minute.
-            // Every pass appends improved cells to the round list of the next
-            // pass (pass 0 to the current one, whose first round follows).
-            for (int pass = 0;; ++pass) {
-                const bool conts = pass == 0;
-                __syncthreads();
-                const int n = conts ? (int)min((int64_t)s_nC[cc], cap)
-                                    : (int)min((int64_t)s_nW[wc], (int64_t)LCAP + cap);
-                if (s_flag) break;
-                if (!conts && n == 0) break;
-                if (n > max_list) max_list = n;
-                c_rounds += !conts;
-                const int wn = conts ? wc : (wc ^ 1);   // round list receiving improvements
-                for (int base = 0; base < n; base += BLOCK) {
-                    const int i = base + tid;
-                    bool act = i < n;
-                    uint32_t c = 0, lab = 0;
-                    int32_t rem[8], cand[8];
-                    uint32_t nbv[8];
-                    CellRec rec;
-                    rec.info = 0;
-                    if (act) {
-                        if (conts) {
-                            const Cont ct = gC[cc][i];
-                            c = ct.c;
-                            lab = ct.label;
+            // Advance one entry per lane: the continuations of p-1 from the
+            // start of p (conts), or a cell whose arrival improved inside p
+            // from that minute.  Improvements are appended to the queue, axes
+            // still travelling at the end of p to the next continuation list.
+            auto process = [&](bool act, uint32_t c, uint32_t lab, int32_t* rem, bool conts) __attribute__((always_inline)) {
+                int32_t cand[8];
+                uint32_t nbv[8];
+                CellRec rec;
+                rec.info = 0;
+                if (act) {
+                    // issue every load of the entry at once: own label,
+                    // cell record and the labels of the in-grid neighbours
+                    const uint32_t own = load_label(&plane[c]);
+                    rec = cells[c];
+                    const int r = (int)(c / (uint32_t)cols), col = (int)(c - (uint32_t)r * (uint32_t)cols);
+                    // axes E NE N NW W SW S SE = bits 0..7; drop those leaving the grid
+                    uint32_t inb = 0xFFu;
+                    if (col + 1 >= cols) inb &= ~0x83u;   // E, NE, SE
+                    if (col == 0) inb &= ~0x38u;          // NW, W, SW
+                    if (r == 0) inb &= ~0x0Eu;            // NE, N, NW
+                    if (r + 1 >= rows) inb &= ~0xE0u;     // SW, S, SE
 #pragma unroll
-                            for (int h = 0; h < 4; ++h) {
-                                rem[2 * h] = (int32_t)(ct.rem[h] & 0xFFFFu);
-                                rem[2 * h + 1] = (int32_t)(ct.rem[h] >> 16);
-                            }
-                            ++c_conts;
-                        } else {
-                            const uint2 ent = i < LCAP ? s_W[wc][i] : gW[wc][i - LCAP];
-                            c = ent.x;
-                            lab = ent.y;
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) rem[k] = D[k];
-                            ++c_entries;
-                        }
-                        // issue every load of the entry at once: own label,
-                        // cell record and the labels of the in-grid neighbours
-                        const uint32_t own = load_label(&plane[c]);
-                        rec = cells[c];
-                        const int r = (int)(c / (uint32_t)cols), col = (int)(c - (uint32_t)r * (uint32_t)cols);
-                        // axes E NE N NW W SW S SE = bits 0..7; drop those leaving the grid
-                        uint32_t inb = 0xFFu;
-                        if (col + 1 >= cols) inb &= ~0x83u;   // E, NE, SE
-                        if (col == 0) inb &= ~0x38u;          // NW, W, SW
-                        if (r == 0) inb &= ~0x0Eu;            // NE, N, NW
-                        if (r + 1 >= rows) inb &= ~0xE0u;     // SW, S, SE
-#pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            nbv[k] = ((inb >> k) & 1u) ? plane[(int64_t)c + off[k]] : kPlaneFill;
-                        act = own == lab;
-                    }
-                    bool keep = false;
-                    if (act) {
-                        const int32_t m0 = conts ? s : (int32_t)(lab & kMinuteMask) + 1;
-                        c_evals += advance<R>(X, rec, c, p, m0, e, nbv, tag, rem, cand);
-                        keep = (rem[0] | rem[1] | rem[2] | rem[3] | rem[4] | rem[5] | rem[6] | rem[7]) != 0;
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) {
-                            cand[k] = kNever;
-                            rem[k] = 0;
-                        }
-                    }
-                    // offer the candidates: atomicMin of real labels, or a
-                    // pending mark where the neighbour's rate is below the
-                    // threshold.  All atomics are issued before any result is
-                    // used so that their latencies overlap.
-                    uint32_t hasm = 0, pendm = 0, impr = 0;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) hasm |= (act && cand[k] != kNever) ? (1u << k) : 0u;
-                    if (use_thr) {
-                        for (uint32_t m = hasm; m != 0u; m &= m - 1u) {
-                            const int k = __ffs(m) - 1;
-                            const uint32_t j = (uint32_t)((int64_t)c + off[k]);
-                            const CellRec rj = cells[j];
-                            ++c_evals;
-                            if (!(head_rate<R>(X, rj, j, (uint32_t)p) > thr)) pendm |= 1u << k;
-                        }
-                    }
-                    uint32_t old[8];
+                    for (int k = 0; k < 8; ++k)
+                        nbv[k] = ((inb >> k) & 1u) ? plane[(int64_t)c + off[k]] : kPlaneFill;
+                    act = own == lab;
+                }
+                bool keep = false;
+                if (act) {
+                    const int32_t m0 = conts ? s : (int32_t)(lab & kMinuteMask) + 1;
+                    c_evals += advance<R>(X, rec, c, p, m0, e, nbv, tag, rem, cand);
+                    keep = (rem[0] | rem[1] | rem[2] | rem[3] | rem[4] | rem[5] | rem[6] | rem[7]) != 0;
+                } else {
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        old[k] = 0u;
-                        if ((hasm >> k) & 1u) {
-                            const uint32_t v = ((pendm >> k) & 1u) ? pendv
-                                                                   : (tag << kMinuteBits) | (uint32_t)cand[k];
-                            old[k] = atomicMin(&plane[(int64_t)c + off[k]], v);
-                        }
+                        cand[k] = kNever;
+                        rem[k] = 0;
                     }
-                    uint32_t newpend = 0;
+                }
+                // offer the candidates: atomicMin of real labels, or a
+                // pending mark where the neighbour's rate is below the
+                // threshold.  All atomics are issued before any result is
+                // used so that their latencies overlap.
+                uint32_t hasm = 0, pendm = 0, impr = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) hasm |= (act && cand[k] != kNever) ? (1u << k) : 0u;
+                if (use_thr) {
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         if (!((hasm >> k) & 1u)) continue;
-                        if ((pendm >> k) & 1u) {
-                            if (old[k] > pendv) newpend |= 1u << k;
+                        const uint32_t j = (uint32_t)((int64_t)c + off[k]);
+                        const CellRec rj = cells[j];
+                        ++c_evals;
+                        if (!(head_rate<R>(X, rj, j, (uint32_t)p) > thr)) pendm |= 1u << k;
+                    }
+                }
+                uint32_t old[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    old[k] = 0u;
+                    if ((hasm >> k) & 1u) {
+                        const uint32_t v = ((pendm >> k) & 1u) ? pendv : (tag << kMinuteBits) | (uint32_t)cand[k];
+                        old[k] = atomicMin(&plane[(int64_t)c + off[k]], v);
+                    }
+                }
+                uint32_t newpend = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if (!((hasm >> k) & 1u)) continue;
+                    if ((pendm >> k) & 1u) {
+                        if (old[k] > pendv) newpend |= 1u << k;
+                        continue;
+                    }
+                    const uint32_t v = (tag << kMinuteBits) | (uint32_t)cand[k];
+                    if (v < old[k]) {
+                        impr |= 1u << k;
+                        if ((old[k] >> kMinuteBits) != tag || (old[k] & kMinuteMask) == kPendingMinute) {
+                            ++c_ign;
+                            if (job.count) atomicAdd(&job.count[(int64_t)c + off[k]], 1u);
+                        }
+                    }
+                }
+                c_cand += __popc(hasm);
+                // append this lane's improved neighbours with one wave scan
+                const int ni = __popc(impr);
+                c_impr += ni;
+                int wtot;
+                const int pre = wave_excl_scan(ni, wtot);
+                if (wtot > 0) {
+                    int wbase = 0;
+                    if (__lane_id() == 0) wbase = atomicAdd(&s_res, wtot);
+                    wbase = __shfl(wbase, 0);
+                    int idx = wbase + pre;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if (!((impr >> k) & 1u)) continue;
+                        q_put(idx, make_uint2((uint32_t)((int64_t)c + off[k]), (tag << kMinuteBits) | (uint32_t)cand[k]));
+                        ++idx;
+                    }
+                    q_commit(wbase, wtot);
+                }
+                if (use_thr) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        append_g(((newpend >> k) & 1u) != 0u, (uint32_t)((int64_t)c + off[k]), gP[pc ^ 1], cap,
+                                 &s_nP[pc ^ 1], &s_flag);
+                }
+                // axes still travelling at the end of p continue in p+1
+                Cont ct;
+                ct.c = c;
+                ct.label = lab;
+#pragma unroll
+                for (int h = 0; h < 4; ++h) ct.rem[h] = (uint32_t)rem[2 * h] | ((uint32_t)rem[2 * h + 1] << 16);
+                append_g(keep, ct, gC[cc ^ 1], cap, &s_nC[cc ^ 1], &s_flag);
+            };
+
+            // continuations of p-1, advanced from the start of p
+            __syncthreads();
+            {
+                const int n = (int)min((int64_t)s_nC[cc], cap);
+                if (n > max_list) max_list = n;
+                for (int base = 0; base < n; base += BLOCK) {
+                    const int i = base + tid;
+                    const bool act = i < n;
+                    uint32_t c = 0, lab = 0;
+                    int32_t rem[8];
+                    if (act) {
+                        const Cont ct = gC[cc][i];
+                        c = ct.c;
+                        lab = ct.label;
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            rem[2 * h] = (int32_t)(ct.rem[h] & 0xFFFFu);
+                            rem[2 * h + 1] = (int32_t)(ct.rem[h] >> 16);
+                        }
+                        ++c_conts;
+                    }
+                    process(act, c, lab, rem, true);
+                }
+            }
+            __syncthreads();
+
+            // label correcting over the period's queue
+            for (;;) {
+                int base = 0, cnt = 0;
+                bool done = false;
+                if (__lane_id() == 0) {
+                    for (;;) {
+                        if (__hip_atomic_load(&s_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                            done = true;
+                            break;
+                        }
+                        const unsigned long long hb =
+                            __hip_atomic_load(&s_hb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        const int h = (int)(hb >> 32), holders = (int)(uint32_t)hb;
+                        const int cm = __hip_atomic_load(&s_commit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (h < cm) {
+                            const int take = min(64, cm - h);
+                            const unsigned long long nhb = ((unsigned long long)(uint32_t)(h + take) << 32) |
+                                                           (unsigned long long)(uint32_t)(holders + 1);
+                            if (atomicCAS(&s_hb, hb, nhb) == hb) {
+                                base = h;
+                                cnt = take;
+                                break;
+                            }
                             continue;
                         }
-                        const uint32_t v = (tag << kMinuteBits) | (uint32_t)cand[k];
-                        if (v < old[k]) {
-                            impr |= 1u << k;
-                            if ((old[k] >> kMinuteBits) != tag || (old[k] & kMinuteMask) == kPendingMinute) {
-                                ++c_ign;
-                                if (job.count) atomicAdd(&job.count[(int64_t)c + off[k]], 1u);
-                            }
+                        // finished when no wave holds a chunk (so none can
+                        // append) and every reserved entry has been taken
+                        const int rs = __hip_atomic_load(&s_res, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (holders == 0 && h == cm && cm == rs) {
+                            done = true;
+                            break;
                         }
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    c_cand += __popc(hasm);
-                    // append this lane's improved neighbours with one wave scan
-                    const int ni = __popc(impr);
-                    c_impr += ni;
-                    int wtot;
-                    const int pre = wave_excl_scan(ni, wtot);
-                    if (wtot > 0) {
-                        const int leader = 0;
-                        int wbase = 0;
-                        if (__lane_id() == leader) wbase = atomicAdd(&s_nW[wn], wtot);
-                        wbase = __shfl(wbase, leader);
-                        int idx = wbase + pre;
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) {
-                            if (!((impr >> k) & 1u)) continue;
-                            const uint2 val = make_uint2((uint32_t)((int64_t)c + off[k]),
-                                                         (tag << kMinuteBits) | (uint32_t)cand[k]);
-                            if (idx < LCAP) s_W[wn][idx] = val;
-                            else if ((int64_t)(idx - LCAP) < cap) gW[wn][idx - LCAP] = val;
-                            else s_flag = 1;
-                            ++idx;
-                        }
-                    }
-                    if (use_thr) {
-#pragma unroll
-                        for (int k = 0; k < 8; ++k)
-                            append_g(((newpend >> k) & 1u) != 0u, (uint32_t)((int64_t)c + off[k]), gP[pc ^ 1], cap,
-                                     &s_nP[pc ^ 1], &s_flag);
-                    }
-                    // axes still travelling at the end of p continue in p+1
-                    Cont ct;
-                    ct.c = c;
-                    ct.label = lab;
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) ct.rem[h] = (uint32_t)rem[2 * h] | ((uint32_t)rem[2 * h + 1] << 16);
-                    append_g(keep, ct, gC[cc ^ 1], cap, &s_nC[cc ^ 1], &s_flag);
                 }
-                __syncthreads();
-                if (!conts) {
-                    if (tid == 0) s_nW[wc] = 0;
-                    wc ^= 1;
+                base = __shfl(base, 0);
+                cnt = __shfl(cnt, 0);
+                done = __shfl((int)done, 0) != 0;
+                if (done) break;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                ++c_rounds;
+                const int i = base + __lane_id();
+                bool act = __lane_id() < cnt && (int64_t)i < qcap;
+                uint32_t c = 0, lab = 0;
+                int32_t rem[8];
+                if (act) {
+                    uint2 ent;
+                    if (i < LQ) {
+                        ent = s_Q[i];
+                    } else {
+                        const uint64_t v = __hip_atomic_load((const uint64_t*)&gQ[i - LQ], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                        ent = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+                    }
+                    c = ent.x;
+                    lab = ent.y;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) rem[k] = D[k];
+                    ++c_entries;
                 }
+                process(act, c, lab, rem, false);
+                if (__lane_id() == 0) atomicAdd(&s_hb, ~0ull);   // one holder fewer
+            }
+            {
+                const int n = s_res;
+                if (n > max_list) max_list = n;
             }
             // ------------------------------------------------- period end
             __syncthreads();
             if (tid == 0) {
                 s_nC[cc] = 0;
                 s_nP[pc] = 0;
+                s_res = s_commit = 0;
+                s_hb = 0ull;
             }
             cc ^= 1;
             pc ^= 1;
@@ -486,7 +579,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         atomicAdd(&s_cnt[kCntEvals], (unsigned long long)c_evals);
         atomicAdd(&s_cnt[kCntCandidates], (unsigned long long)c_cand);
         atomicAdd(&s_cnt[kCntImprovements], (unsigned long long)c_impr);
-        if (tid == 0) s_cnt[kCntRounds] = (unsigned long long)c_rounds;
+        if (__lane_id() == 0) atomicAdd(&s_cnt[kCntRounds], (unsigned long long)c_rounds);   // chunks, per wave
         atomicMax(&s_cnt[kCntMaxList], (unsigned long long)max_list);
         if (slots.item_slot) {
             if (tid == 0) slots.item_slot[item] = make_int2(slot, (int)tag);
