@@ -340,6 +340,48 @@ def test_device_outputs_accumulate_on_default_stream(sim):
     sim.unset_weather(x)
 
 
+def test_graph_replays_match_eager_runs(sim):
+    """Synchronous calls replay one captured hipGraph (fills, propagation,
+    dense outputs).  Replays interleaved with eager library work (rate
+    fields, another request) each equal an eager run of the same request
+    through a serving lane, which launches without graphs."""
+    _say("graph replays")
+    w = inputs.batched_monte_carlo(side=96, reps=12, n_scenarios=3, n_periods=8)
+    land = sim.load_landscape(w.fuel, w.elev)
+    x = sim.set_weather(w.weather)
+    req = Request(landscape=land, weather=x, **request_kwargs(w))
+    other = Request(landscape=land, weather=x, **request_kwargs(w, reps=3, seed=99))
+    with Simulator(0) as eager_sim:
+        land2 = eager_sim.load_landscape(w.fuel, w.elev)
+        x2 = eager_sim.set_weather(w.weather)
+        t, _ = eager_sim.submit(Request(landscape=land2, weather=x2, **request_kwargs(w)))
+        eager = eager_sim.wait(t)
+    for k in range(6):
+        g = sim.simulate(req)
+        assert_same_outputs(g, eager, where=f"replay {k}")
+        sim.eval_ros(land, x, scenario=k % 3, period=k, rep=k)   # eager work between replays
+        if k == 2:
+            sim.simulate(other)      # another launch sequence: the next call captures anew
+    sim.unload_landscape(land)
+    sim.unset_weather(x)
+
+
+def test_autotune_keeps_results(sim):
+    _say("autotune")
+    w = inputs.batched_monte_carlo(side=128, reps=40, n_scenarios=4, n_periods=8)
+    land = sim.load_landscape(w.fuel, w.elev)
+    x = sim.set_weather(w.weather)
+    req = Request(landscape=land, weather=x, **request_kwargs(w))
+    before = sim.simulate(req)
+    sim.autotune(req)
+    after = sim.simulate(req)
+    st = sim.stats()
+    assert st["block_threads"] in (64, 128, 256, 512, 1024)
+    assert_same_outputs(after, {k: np.asarray(v) for k, v in before.items()}, where="after autotune")
+    sim.unload_landscape(land)
+    sim.unset_weather(x)
+
+
 # ------------------------------------------------------- medium workloads
 
 def test_single_fire_512_fp64(sim):
