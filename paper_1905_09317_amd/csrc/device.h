@@ -17,7 +17,6 @@ __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ float m_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
 __device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
@@ -44,6 +43,30 @@ __device__ __forceinline__ double recip(double b) {
     r = fma(fma(-b, r, 1.0), r, r);
     r = fma(fma(-b, r, 1.0), r, r);
     return r;
+}
+
+// Powers on the rate path: x >= 0 (a rate-curve base, 1 - exp(-0.03 WSV),
+// or a wind speed) and y a positive fuel constant below 5, as exp(y ln x).
+// A relative error of about one ulp in ln x becomes an absolute error of
+// |y ln x| ulp in the exponent, so the result keeps a relative error of a
+// few ulp for these bases, at a third of the instructions of the general
+// pow() (which rounds exactly and handles every special case).  FP32 uses
+// the hardware base-2 logarithm and exponential.  x = 0 gives 0.
+__device__ __forceinline__ double rate_pow(double x, double y) { return exp(y * log(x)); }
+__device__ __forceinline__ float rate_pow(float x, float y) { return exp2f(y * log2f(x)); }
+
+// cos(2 pi u) for the Box-Muller draw, without a general argument reduction.
+__device__ __forceinline__ double cos_2pi(double u) { return cospi(2.0 * u); }
+__device__ __forceinline__ float cos_2pi(float u) { return cospif(2.0f * u); }
+
+// ln(1 - x) for 0 <= x <= 0.99 in FP32 from one logarithm: with u = 1 - x
+// rounded, ln(u) x / (1 - u) corrects the rounding of u (the log1p form of
+// Goldberg, 1991; 1 - u is exact here), so a small x keeps its full
+// relative precision.
+__device__ __forceinline__ float log_1m(float x) {
+    const float u = 1.0f - x;
+    if (u == 1.0f) return -x;
+    return logf(u) * (x * __builtin_amdgcn_rcpf(1.0f - u));
 }
 
 template <typename R> struct Const;
@@ -93,7 +116,7 @@ struct CoefR {
 // Rate of spread of one unmixed fuel: a (1 - exp(-b ISI))^c.
 template <typename R>
 __device__ __forceinline__ R rsi_pure(const CoefR<R>& k, R isi) {
-    return k.a * m_pow(-m_expm1(-k.b * isi), k.c);
+    return k.a * rate_pow(-m_expm1(-k.b * isi), k.c);
 }
 
 // Fill one table row from FFMC, BUI, wind speed (km/h) and the azimuth the
@@ -182,13 +205,13 @@ __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, d
 }
 
 // The same in FP32 for the ordinary branch (WSE <= 40 km/h).  ln(1 - x) is
-// taken as log1p(-x), so a gentle slope (x close to the zero-slope value)
+// taken with log1p accuracy (log_1m), so a gentle slope (x close to the zero-slope value)
 // keeps full relative precision in ISF, and WSE = ln(ISF / ISZ) / 0.05039
 // then carries an absolute error of a few 1e-6 km/h.  Near and above the
 // 40 km/h branch point the caller switches to slope_wind in FP64.
 __device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float sfc, float g) {
     const float x = sfc * g;
-    return -m_log1p(-(x > 0.99f ? 0.99f : x)) * recip(k.b);
+    return -log_1m(x > 0.99f ? 0.99f : x) * recip(k.b);
 }
 
 __device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, float sfc, float sfd,
@@ -244,7 +267,7 @@ __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const C
     // 8.729 (1 - exp(-0.030 WSV))^2.155, as one power per lane
     const bool grass = f >= kO1a;
     const R lbase = grass ? wsv : -m_expm1((R)-0.030 * wsv);
-    const R lpow = m_pow(lbase, grass ? (R)0.464 : (R)2.155);
+    const R lpow = rate_pow(lbase, grass ? (R)0.464 : (R)2.155);
     out.lbm1 = grass ? ((wsv >= (R)1) ? (R)1.1 * lpow - (R)1 : (R)0) : (R)8.729 * lpow;
     out.lb = (R)1 + out.lbm1;
     out.wx = wx;
@@ -270,7 +293,7 @@ __device__ __forceinline__ R noise_mult(uint64_t seed, uint32_t cell, uint32_t p
     const uint4 x = draw(seed, cell, period, rep, 0u);
     const R u1 = ((R)(x.x >> 8) + (R)1) * (R)(1.0 / 16777216.0);
     const R u2 = unit24<R>(x.y);
-    const R z = m_sqrt((R)-2 * m_log(u1)) * m_cos((R)2 * Const<R>::pi * u2);
+    const R z = m_sqrt((R)-2 * m_log(u1)) * cos_2pi(u2);
     return m_exp(sigma * z - (R)0.5 * sigma * sigma);
 }
 
