@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, factors from a plain 256 MiB
 # copy), valid for the kernel sources whose digest is given; reported as
 # roofline.traffic only while the sources are unchanged.
-KERNEL_SOURCES = ("propagate.hip", "device.h", "types.h", "fuel_table.h")
+KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
     "single-fire-2048x2048-48h": ("b178d75f4888be5f", 10_055_413),
     "batched-mc-1024x1024-2048reps": ("b178d75f4888be5f", 39_217_674_059),
@@ -263,6 +263,9 @@ def main():
                     help="also time this many replications one per launch (default: 64 for "
                          "multi-replication workloads, 0 = off)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--rep-order", type=int, default=1, choices=[0, 1],
+                    help="1: groups running several replications take the longest predicted "
+                         "first (default); 0: index order")
     ap.add_argument("--queries", type=int, default=1000, help="served: queries in the stream")
     ap.add_argument("--rate", type=float, default=50.0, help="served: Poisson arrivals per second")
     ap.add_argument("--lanes", type=int, default=4, help="served: concurrent serving lanes")
@@ -300,6 +303,7 @@ def main():
                   precision=w.precision, ignition_mode=w.ignition_mode,
                   ignition_cell=w.ignition_cell, scenario_mode=w.scenario_mode,
                   scenario=w.scenario, outputs=dense_outputs(w), device_out=True)
+    sim.set_rep_order(args.rep_order)
     if args.autotune:
         sim.autotune(req)
     if args.block:
@@ -353,6 +357,7 @@ def main():
                    "rate_precision": ["fp64", "fp32"][w.precision],
                    "ignition": ["fixed", "uniform-burnable", "nearest-centre"][w.ignition_mode],
                    "block_threads": st["block_threads"], "grid_blocks": st["grid_blocks"],
+                   "rep_order": st["rep_order"],
                    "list_capacity": st["list_capacity"]},
         "burn_maps_per_s": w.reps / (ms / 1e3),
         "burned_cells": burned,

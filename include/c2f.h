@@ -191,6 +191,16 @@ c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capa
  * the request allows it.  Results are the same either way. */
 c2f_status c2f_set_period_split(c2f_ctx* ctx, int32_t mode);
 
+/* Replication order.  When a launch has more replications than resident
+ * work groups, each group runs several one after another, and a long
+ * replication taken last keeps its group busy after the others finish.
+ * mode 1 (default): before the launch, a small kernel predicts each
+ * replication's length from the head rate at its ignition cell over the
+ * run (Sections 3.1 and 3.4) and groups take the longest first; mode 0:
+ * index order.  Only the schedule changes: every replication keeps its
+ * index, random streams and output row, so results are identical. */
+c2f_status c2f_set_rep_order(c2f_ctx* ctx, int32_t mode);
+
 /* Pick block size and list capacity for requests like `representative` by
  * timing candidates on the device; the choice is kept for requests of the
  * same grid size and replication count. */
@@ -210,7 +220,7 @@ typedef struct {
     int32_t block_threads, grid_blocks;
     int64_t list_capacity;
     int32_t period_split;    /* 1 if the launch ran period by period with precomputed rates */
-    int32_t reserved;
+    int32_t rep_order;       /* 1 if groups took replications longest-predicted first */
 } c2f_run_stats;
 c2f_status c2f_get_stats(const c2f_ctx* ctx, c2f_run_stats* out);
 

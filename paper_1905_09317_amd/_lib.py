@@ -43,7 +43,7 @@ class RunStats(ctypes.Structure):
                 ("rounds", ctypes.c_int64), ("continuations", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("block_threads", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("list_capacity", ctypes.c_int64),
-                ("period_split", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("period_split", ctypes.c_int32), ("rep_order", ctypes.c_int32)]
 
 
 class TicketInfo(ctypes.Structure):
@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
         "c2f_set_serving": ([P, i32, i32, i32, u64], i32),
         "c2f_get_memory": ([P, pp(u64), pp(u64)], i32),
         "c2f_set_period_split": ([P, i32], i32),
+        "c2f_set_rep_order": ([P, i32], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -109,4 +110,4 @@ DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
             "c2f_simulate_batch", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
             "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
-            "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_period_split")
+            "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_period_split", "c2f_set_rep_order")

@@ -210,6 +210,11 @@ class Simulator:
         """0 or 1: never; 2: whenever the request allows it (same results)."""
         self._check(self._L.c2f_set_period_split(self._ctx, int(mode)))
 
+    def set_rep_order(self, mode: int = 1):
+        """1: work groups that run several replications take the longest
+        predicted first (default); 0: in index order.  Same results."""
+        self._check(self._L.c2f_set_rep_order(self._ctx, int(mode)))
+
     def autotune(self, req: Request | None = None, **kw):
         req = req or Request(**kw)
         p = req.params()

@@ -111,6 +111,9 @@ struct Exec {
     size_t staging_bytes = 0;
     int2* item_slot = nullptr;        // {slot, tag} per item of a launch
     int32_t item_slot_cap = 0;
+    unsigned long long* order_keys = nullptr;   // replication order: a key
+    int32_t* order = nullptr;                   // and a position per item
+    int32_t order_cap = 0;
     SplitState* split_st = nullptr;   // period-split launches: state per slot,
     int32_t split_st_cap = 0;
     SplitRegion* split_reg = nullptr; // the shared region record,
@@ -177,6 +180,7 @@ struct c2f_ctx {
 
     std::mutex tunemu;
     int32_t split_mode = 0;   // period-split launches: 0/1 never, 2 whenever possible
+    int32_t rep_order = 1;    // 1: longest predicted replications first when groups run several
     int32_t block_override = 0;
     int64_t cap_override = 0;
     std::map<TuneKey, TuneVal> tune;
@@ -321,6 +325,10 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     dev_free(ctx, ex.item_slot, (size_t)ex.item_slot_cap * sizeof(int2));
     ex.item_slot = nullptr;
     ex.item_slot_cap = 0;
+    dev_free(ctx, ex.order_keys, (size_t)ex.order_cap * kOrderBytesPerItem);
+    ex.order_keys = nullptr;
+    ex.order = nullptr;
+    ex.order_cap = 0;
     dev_free(ctx, ex.split_st, (size_t)ex.split_st_cap * sizeof(SplitState));
     dev_free(ctx, ex.split_reg, sizeof(SplitRegion));
     dev_free(ctx, ex.rate_cache, (size_t)ex.rate_cache_cells * sizeof(uint4));
@@ -476,6 +484,23 @@ c2f_status ensure_item_slots(c2f_ctx* ctx, Exec& ex, int32_t n) {
     return C2F_OK;
 }
 
+// Key and position per item for the replication order (one allocation).
+c2f_status ensure_order(c2f_ctx* ctx, Exec& ex, int32_t n) {
+    if (n > ex.order_cap) {
+        drop_graph(ex);
+        dev_free(ctx, ex.order_keys, (size_t)ex.order_cap * kOrderBytesPerItem);
+        ex.order_keys = nullptr;
+        ex.order = nullptr;
+        ex.order_cap = 0;
+        const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
+        c2f_status st = dev_alloc(ctx, (void**)&ex.order_keys, (size_t)cap * kOrderBytesPerItem);
+        if (st != C2F_OK) return st;
+        ex.order = (int32_t*)(ex.order_keys + cap);
+        ex.order_cap = cap;
+    }
+    return C2F_OK;
+}
+
 c2f_status ensure_split(c2f_ctx* ctx, Exec& ex, int32_t n, int64_t cells) {
     if (n > ex.split_st_cap) {
         drop_graph(ex);
@@ -575,10 +600,16 @@ LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t
             lp.block = it->second.block;
             lp.cap = it->second.list_cap;
         } else {
-            // few replications on a large grid: wide groups.  The FP64
-            // kernel keeps 512 threads (2 waves per SIMD, 256 VGPRs); at 1024
-            // it would be held to 128 VGPRs and spill.
-            lp.block = cells >= (1 << 22) && total_items <= 16 ? (precision == 1 ? 1024 : 512) : 256;
+            // At most one replication per compute unit on a large grid:
+            // wide groups, since nothing else would use the unit.  FP64
+            // keeps 512 threads (2 waves per SIMD, 256 VGPRs); at 1024 it
+            // would be held to 128 VGPRs and spill (8192^2 x 64 reps: 10.1
+            // ms at 512, 12.8 at 256, 18.8 at 1024).  FP32 single fires take
+            // 1024 threads despite a small spill.
+            if (cells >= (1 << 20) && total_items <= ctx->n_cu)
+                lp.block = (precision == 1 && total_items <= 16) ? 1024 : 512;
+            else
+                lp.block = 256;
             lp.cap = default_list_cap(cells, total_items);
         }
         if (ctx->block_override) lp.block = ctx->block_override;
@@ -608,11 +639,14 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     if (st != C2F_OK) return st;
     bool dense = false;
     for (int k : idx) dense |= plans[k].scar || plans[k].arr_minute || plans[k].arr_period;
-    int32_t split_mode;
+    int32_t split_mode, rep_order;
     {
         std::lock_guard<std::mutex> lk(ctx->tunemu);
         split_mode = ctx->split_mode;
+        rep_order = ctx->rep_order;
     }
+    int32_t max_periods = 0;
+    for (int k : idx) max_periods = std::max(max_periods, P[k].n_periods);
     // Period-split form: one request whose rates do not depend on the
     // replication (no noise, nearest rounding, one scenario, no threshold).
     const c2f_sim_params& p0 = P[idx[0]];
@@ -685,6 +719,12 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             st = ensure_item_slots(ctx, ex, total);
             if (st != C2F_OK) return st;
         }
+        // groups that run several replications take the longest predicted first
+        const bool ordered = rep_order == 1 && !split && total > lp.grid && max_periods <= 65535;
+        if (ordered) {
+            st = ensure_order(ctx, ex, total);
+            if (st != C2F_OK) return st;
+        }
         if (split) {
             st = ensure_split(ctx, ex, total, max_cells);
             if (st == C2F_ENOMEM && lp.grid > 1) {
@@ -694,7 +734,8 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             if (st != C2F_OK) return st;
         }
         const int64_t limit = std::min(lp.cap, ex.list_cap);
-        Slots sl{ex.planes, ex.plane_cells, ex.lists, ex.list_cap, limit, ex.tags, defer ? ex.item_slot : nullptr};
+        Slots sl{ex.planes,  ex.plane_cells, ex.lists, ex.list_cap, limit, ex.tags, defer ? ex.item_slot : nullptr,
+                 ordered ? ex.order : nullptr};
         // key of the launch sequence for graph reuse
         std::vector<uint64_t> key = {(uint64_t)(uintptr_t)ex.d_jobs, idx.size(), (uint64_t)total,
                                      (uint64_t)lp.block, (uint64_t)lp.grid, (uint64_t)precision,
@@ -703,7 +744,8 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
                                      (uint64_t)(uintptr_t)ex.stream, (uint64_t)defer,
                                      (uint64_t)(uintptr_t)ex.item_slot, (uint64_t)split,
                                      (uint64_t)(uintptr_t)ex.split_st, (uint64_t)(uintptr_t)ex.rate_cache,
-                                     (uint64_t)P[idx[0]].n_periods};
+                                     (uint64_t)P[idx[0]].n_periods, (uint64_t)ordered,
+                                     (uint64_t)(uintptr_t)ex.order_keys, (uint64_t)max_periods};
         for (int k : idx) {
             key.push_back((uint64_t)(uintptr_t)plans[k].count);
             key.push_back((uint64_t)Ls[k]->ncells());
@@ -722,6 +764,11 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
                     e = launch_fill_u32(plans[k].count, (size_t)Ls[k]->ncells(), 0u, ex.stream);
                     if (e != hipSuccess) return e;
                 }
+            }
+            if (ordered) {
+                e = launch_order(precision, ex.d_jobs, (int)idx.size(), total, max_periods, ex.order_keys, ex.order,
+                                 ex.stream);
+                if (e != hipSuccess) return e;
             }
             if (split)
                 e = launch_split(precision, lp.block, ex.d_jobs, total, P[idx[0]].n_periods, 4 * ctx->n_cu, sl,
@@ -784,6 +831,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             ex.last.grid_blocks = lp.grid;
             ex.last.list_capacity = limit;
             ex.last.period_split = split ? 1 : 0;
+            ex.last.rep_order = ordered ? 1 : 0;
             return C2F_OK;
         }
         ++ex.last.relaunches;
@@ -931,6 +979,9 @@ size_t batch_growth(c2f_ctx* ctx, const Exec& ex, const std::vector<std::shared_
         max_cells = std::max(max_cells, cells[pr]);
     }
     size_t g = exec_growth(ex, grid, max_cells, cap, stage, (int32_t)batch.size());
+    const int32_t n_items = std::max(items[0], items[1]);
+    if (n_items > grid && n_items > ex.order_cap)   // a launch in replication order
+        g += ((size_t)pow2_at_least(std::max(n_items, 64)) - (size_t)ex.order_cap) * kOrderBytesPerItem;
     if (batch.size() == 1 && max_cells > ex.rate_cache_cells)   // a possible period-split launch
         g += (size_t)((ex.round_up ? pow2_at_least(max_cells) : max_cells) - ex.rate_cache_cells) * sizeof(uint4);
     return g;
@@ -1437,6 +1488,15 @@ c2f_status c2f_set_period_split(c2f_ctx* ctx, int32_t mode) {
     if (mode < 0 || mode > 2) return fail(ctx, C2F_EINVAL, "mode must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(ctx->tunemu);
     ctx->split_mode = mode;
+    return C2F_OK;
+}
+
+c2f_status c2f_set_rep_order(c2f_ctx* ctx, int32_t mode) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (mode < 0 || mode > 1) return fail(ctx, C2F_EINVAL, "mode must be 0 or 1");
+    std::lock_guard<std::mutex> lk(ctx->tunemu);
+    ctx->rep_order = mode;
     return C2F_OK;
 }
 

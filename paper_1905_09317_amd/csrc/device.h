@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "fuel_table.h"
+#include "ln64.h"
 #include "types.h"
 
 namespace c2f {
@@ -17,7 +18,7 @@ __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float m_expm1(float x) { return expm1f(x); }
-__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ double m_log(double x) { return ln_f64(x); }
 __device__ __forceinline__ float m_log(float x) { return logf(x); }
 __device__ __forceinline__ double m_pow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float m_pow(float x, float y) { return powf(x, y); }
@@ -52,7 +53,7 @@ __device__ __forceinline__ double recip(double b) {
 // few ulp for these bases, at a third of the instructions of the general
 // pow() (which rounds exactly and handles every special case).  FP32 uses
 // the hardware base-2 logarithm and exponential.  x = 0 gives 0.
-__device__ __forceinline__ double rate_pow(double x, double y) { return exp(y * log(x)); }
+__device__ __forceinline__ double rate_pow(double x, double y) { return exp(y * ln_f64(x)); }
 __device__ __forceinline__ float rate_pow(float x, float y) { return exp2f(y * log2f(x)); }
 
 // cos(2 pi u) for the Box-Muller draw, without a general argument reduction.
@@ -184,7 +185,7 @@ __device__ __forceinline__ R rsi_fuel(const CoefR<R>* coef, int f, R isi, const 
 __device__ __forceinline__ double isf_curve(const CoefR<double>& k, double sfc, double g) {
     double t = 1.0 - sfc * g;
     if (t < 0.01) t = 0.01;
-    return -log(t) * recip(k.b);
+    return -ln_f64(t) * recip(k.b);
 }
 
 __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, double sfc, double sfd,
@@ -197,9 +198,9 @@ __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, d
     } else {
         isf = isf_curve(coef[f], sfc, row[kRowG + f]);
     }
-    double wse = log(isf * recip(isz)) * (1.0 / 0.05039);
+    double wse = ln_f64(isf * recip(isz)) * (1.0 / 0.05039);
     if (wse > 40.0) {
-        wse = (isf < 0.999 * 2.496 * ff) ? 28.0 - log(1.0 - isf * recip(2.496 * ff)) * (1.0 / 0.0818) : 112.45;
+        wse = (isf < 0.999 * 2.496 * ff) ? 28.0 - ln_f64(1.0 - isf * recip(2.496 * ff)) * (1.0 / 0.0818) : 112.45;
     }
     return wse;
 }
@@ -397,6 +398,31 @@ struct RateCtx {
     int rounding;
     uint32_t rep;
 };
+
+// Weather scenario and ignition cell of replication `rep` of a job
+// (Section 3.1, uncertainty sources (1) and (3)): a fixed scenario or
+// (x S) >> 32 from Philox tag 4; a fixed cell, the burnable cell (x |B|) >> 32
+// of the row-major burnable list from tag 3, or the burnable cell nearest
+// the centre.  ign = -1 when the landscape has no burnable cell.
+__device__ __forceinline__ void rep_draws(const Job& job, uint32_t rep, int& scen, int& ign) {
+    scen = job.scen_fixed;
+    if (job.scen_mode == 1) {
+        const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 4u);
+        scen = (int)(((uint64_t)x.x * (uint64_t)job.n_scen) >> 32);
+    }
+    ign = -1;
+    if (job.ign_mode == 0) {
+        ign = job.ign_cell;
+    } else if (job.ign_mode == 1) {
+        const int nbn = job.land->n_burnable;
+        if (nbn > 0) {
+            const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
+            ign = job.burnable[((uint64_t)x.x * (uint64_t)nbn) >> 32];
+        }
+    } else {
+        ign = job.land->centre_cell;
+    }
+}
 
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
 // the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.

@@ -37,6 +37,12 @@ hipError_t launch_split(int precision, int block, const Job* jobs, int total, in
                         const Slots& slots, SplitState* st, SplitRegion* reg, uint4* cache, RunCounters* rc,
                         hipStream_t s);
 
+// Replication order of a launch whose work groups each run several items:
+// keys[item] = predicted head-fire travel (zeroed first), order = items by
+// decreasing key.  max_periods <= 65535.
+hipError_t launch_order(int precision, const Job* jobs, int n_jobs, int total_items, int max_periods,
+                        unsigned long long* keys, int32_t* order, hipStream_t s);
+
 // Dense per-replication outputs of a launch whose items each kept a slot
 // (slots.item_slot filled by the propagation, cleared to -1 before it);
 // total <= 65535; nothing is written if the launch overflowed.

@@ -52,6 +52,9 @@ __device__ __forceinline__ int wave_rank(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Value of x in lane `lane` (wave-uniform) without a trip through LDS.
+__device__ __forceinline__ int lane_value(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
 // One LDS atomic per wave reserves slots for the appending lanes.
 __device__ __forceinline__ int wave_reserve(bool pred, int* counter, uint64_t& m) {
     m = __ballot(pred);
@@ -59,7 +62,7 @@ __device__ __forceinline__ int wave_reserve(bool pred, int* counter, uint64_t& m
     const int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
     if (__lane_id() == leader) base = atomicAdd(counter, (int)__popcll(m));
-    return __shfl(base, leader) + wave_rank(m);
+    return lane_value(base, leader) + wave_rank(m);
 }
 
 // Round lists: the first lcap entries in LDS, the rest in the slot's global list.
@@ -84,18 +87,6 @@ __device__ __forceinline__ void append_g(bool pred, const T& val, T* glob, int64
     }
 }
 
-// Exclusive prefix sum of `v` over the lanes of a wave, and the wave total.
-__device__ __forceinline__ int wave_excl_scan(int v, int& total) {
-    const int lane = __lane_id();
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
-    total = __shfl(x, 63);
-    return x - v;
-}
 
 // Advance cell c (label lab) through period p from minute m0 to e.  nbv[k]
 // is the label of neighbour k read at the start of the pass; rem[k] holds
@@ -190,6 +181,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         if (tid == 0) {
             int it = atomicAdd(&rc->next_item, 1);
             if (__hip_atomic_load(&rc->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total_items;
+            else if (slots.order && it < total_items) it = slots.order[it];
             s_item = it;
         }
         __syncthreads();
@@ -224,23 +216,8 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             s_nC[0] = s_nC[1] = s_nP[0] = s_nP[1] = 0;
             s_flag = 0;
             for (int k = 0; k < kNumCounters; ++k) s_cnt[k] = 0;
-            int scen = job.scen_fixed;
-            if (job.scen_mode == 1) {
-                const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 4u);
-                scen = (int)(((uint64_t)x.x * (uint64_t)job.n_scen) >> 32);
-            }
-            int ign = -1;
-            if (job.ign_mode == 0) {
-                ign = job.ign_cell;
-            } else if (job.ign_mode == 1) {
-                const int nbn = job.land->n_burnable;
-                if (nbn > 0) {
-                    const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
-                    ign = job.burnable[((uint64_t)x.x * (uint64_t)nbn) >> 32];
-                }
-            } else {
-                ign = job.land->centre_cell;
-            }
+            int scen, ign;
+            rep_draws(job, rep, scen, ign);
             s_scen = scen;
             s_ign = ign;
         }
@@ -307,7 +284,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             if (m == 0) return;
             int wbase = 0;
             if (__lane_id() == 0) wbase = atomicAdd(&s_res, (int)__popcll(m));
-            wbase = __shfl(wbase, 0);
+            wbase = lane_value(wbase, 0);
             if (pred) q_put(wbase + wave_rank(m), val);
             q_commit(wbase, (int)__popcll(m));
         };
@@ -430,23 +407,28 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                     }
                 }
                 c_cand += __popc(hasm);
-                // append this lane's improved neighbours with one wave scan
-                const int ni = __popc(impr);
-                c_impr += ni;
-                int wtot;
-                const int pre = wave_excl_scan(ni, wtot);
+                // append the wave's improved neighbours axis by axis: one
+                // ballot per axis gives each lane its place in the range
+                c_impr += __popc(impr);
+                uint64_t am[8];
+                int wtot = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    am[k] = __ballot((impr >> k) & 1u);
+                    wtot += (int)__popcll(am[k]);
+                }
                 if (wtot > 0) {
                     int wbase = 0;
                     if (__lane_id() == 0) wbase = atomicAdd(&s_res, wtot);
-                    wbase = __shfl(wbase, 0);
-                    int idx = wbase + pre;
+                    int idx = lane_value(wbase, 0);
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        if (!((impr >> k) & 1u)) continue;
-                        q_put(idx, make_uint2((uint32_t)((int64_t)c + off[k]), (tag << kMinuteBits) | (uint32_t)cand[k]));
-                        ++idx;
+                        if ((impr >> k) & 1u)
+                            q_put(idx + wave_rank(am[k]),
+                                  make_uint2((uint32_t)((int64_t)c + off[k]), (tag << kMinuteBits) | (uint32_t)cand[k]));
+                        idx += (int)__popcll(am[k]);
                     }
-                    q_commit(wbase, wtot);
+                    q_commit(lane_value(wbase, 0), wtot);
                 }
                 if (use_thr) {
 #pragma unroll
@@ -524,9 +506,9 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                         __builtin_amdgcn_s_sleep(1);
                     }
                 }
-                base = __shfl(base, 0);
-                cnt = __shfl(cnt, 0);
-                done = __shfl((int)done, 0) != 0;
+                base = lane_value(base, 0);
+                cnt = lane_value(cnt, 0);
+                done = lane_value((int)done, 0) != 0;
                 if (done) break;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 ++c_rounds;

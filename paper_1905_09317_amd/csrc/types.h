@@ -92,6 +92,9 @@ struct Cont {
 //   P[2] pending cells, uint32
 constexpr int64_t kSlotListBytesPerEntry = 2 * 8 + 2 * 24 + 2 * 4;
 
+// Replication order of a launch: a 64-bit key and a 32-bit position per item.
+constexpr size_t kOrderBytesPerItem = 8 + 4;
+
 // Work slots: one per resident work group.  Each owns an arrival plane of
 // plane_cells labels, its lists and a tag.  A launch uses list_limit entries
 // of each list; the buffers may hold more from an earlier, larger launch.
@@ -107,6 +110,9 @@ struct Slots {
     // propagation by a grid-wide kernel: item_slot[item] = {slot, tag}.
     // NULL: each work group writes them at the end of its replication.
     int2* item_slot;
+    // order[n] = the item the n-th fetch of a work group takes (longest
+    // predicted replications first); NULL: item n.
+    const int32_t* order;
 };
 
 // Period-split launches (rates that do not depend on the replication):

@@ -382,6 +382,31 @@ def test_autotune_keeps_results(sim):
     sim.unset_weather(x)
 
 
+def test_rep_order_keeps_results(sim):
+    """More replications than resident groups: groups take the longest
+    predicted replications first, which changes only the schedule."""
+    _say("replication order")
+    w = inputs.batched_monte_carlo(side=64, reps=700, n_scenarios=5, n_periods=6)
+    land = sim.load_landscape(w.fuel, w.elev)
+    x = sim.set_weather(w.weather)
+    outs = ("burn_count", "burned_cells", "ignition_cell", "scenario")
+    req = Request(landscape=land, weather=x, outputs=outs, **request_kwargs(w))
+    sim.set_rep_order(0)
+    plain = sim.simulate(req)
+    st0 = sim.stats()
+    sim.set_rep_order(1)
+    ordered = sim.simulate(req)
+    st1 = sim.stats()
+    assert st0["rep_order"] == 0 and st1["rep_order"] == 1, (st0, st1)
+    assert st1["grid_blocks"] < w.reps
+    assert_same_outputs(ordered, plain, outs, where="ordered vs index order")
+    ref = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w, reps=4))
+    for k in ("burned_cells", "ignition_cell", "scenario"):
+        np.testing.assert_array_equal(np.asarray(ordered[k])[:4], ref[k], err_msg=k)
+    sim.unload_landscape(land)
+    sim.unset_weather(x)
+
+
 # ------------------------------------------------------- medium workloads
 
 def test_single_fire_512_fp64(sim):
