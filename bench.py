@@ -41,9 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # roofline.traffic only while the sources are unchanged.
 KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
-    "single-fire-2048x2048-48h": ("b178d75f4888be5f", 10_055_413),
-    "batched-mc-1024x1024-2048reps": ("b178d75f4888be5f", 39_217_674_059),
-    "large-8192x8192-64reps-72h": ("b178d75f4888be5f", 796_582_082),
+    "single-fire-2048x2048-48h": ("723875dc0372f922", 10_372_525),
+    "batched-mc-1024x1024-2048reps": ("723875dc0372f922", 40_676_519_988),
+    "large-8192x8192-64reps-72h": ("723875dc0372f922", 793_506_655),
 }
 
 
