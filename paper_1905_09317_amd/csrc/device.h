@@ -8,6 +8,7 @@
 
 #include "fuel_table.h"
 #include "ln64.h"
+#include "small_div.h"
 #include "types.h"
 
 namespace c2f {
@@ -77,12 +78,15 @@ template <> struct Const<float> { static constexpr float pi = 3.1415926535897932
 // --------------------------------------------------------------- Philox
 // Philox4x32-10 block function (Salmon et al., SC'11): ten rounds of two
 // 32x32->64 multiplies, key bumped by the Weyl constants between rounds.
+// Each product is formed once in 64 bits (one v_mad_u64_u32 instead of a
+// low and a high multiply).
 __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * x.x, hi0 = __umulhi(0xD2511F53u, x.x);
-        const uint32_t lo1 = 0xCD9E8D57u * x.z, hi1 = __umulhi(0xCD9E8D57u, x.z);
-        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x.z;
+        x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.w ^ k1,
+                       (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -191,12 +195,14 @@ __device__ __forceinline__ double isf_curve(const CoefR<double>& k, double sfc, 
 __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, double sfc, double sfd,
                                           const double* row, const LandR<double>& L) {
     const double ff = row[0], isz = row[1];
-    double isf;
-    if (f == kM1 || f == kM2) {
-        isf = L.pc_w * isf_curve(coef[kC2], sfc, row[kRowG + kC2]) +
-              (1.0 - L.pc_w) * isf_curve(coef[kD1], sfd, row[kRowG + kD1]);
-    } else {
-        isf = isf_curve(coef[f], sfc, row[kRowG + f]);
+    // every lane inverts its own (or the C-2) curve; the D-1 curve only runs
+    // when some lane of the wave is mixedwood
+    const bool mixed = (f == kM1 || f == kM2);
+    const int fa = mixed ? (int)kC2 : f;
+    double isf = isf_curve(coef[fa], sfc, row[kRowG + fa]);
+    if (__any(mixed)) {
+        const double d1 = isf_curve(coef[kD1], sfd, row[kRowG + kD1]);
+        if (mixed) isf = L.pc_w * isf + (1.0 - L.pc_w) * d1;
     }
     double wse = ln_f64(isf * recip(isz)) * (1.0 / 0.05039);
     if (wse > 40.0) {
@@ -217,12 +223,12 @@ __device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float sfc, f
 
 __device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, float sfc, float sfd,
                                               const float* row, const LandR<float>& L) {
-    float isf;
-    if (f == kM1 || f == kM2) {
-        isf = L.pc_w * isf_curve32(coef[kC2], sfc, row[kRowG + kC2]) +
-              (1.0f - L.pc_w) * isf_curve32(coef[kD1], sfd, row[kRowG + kD1]);
-    } else {
-        isf = isf_curve32(coef[f], sfc, row[kRowG + f]);
+    const bool mixed = (f == kM1 || f == kM2);
+    const int fa = mixed ? (int)kC2 : f;
+    float isf = isf_curve32(coef[fa], sfc, row[kRowG + fa]);
+    if (__any(mixed)) {
+        const float d1 = isf_curve32(coef[kD1], sfd, row[kRowG + kD1]);
+        if (mixed) isf = L.pc_w * isf + (1.0f - L.pc_w) * d1;
     }
     return m_log(isf * recip(row[1])) * (1.0f / 0.05039f);
 }
@@ -257,13 +263,15 @@ __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const C
         wy += wse * ((R)gn * ig);
     }
     const R wsv = m_sqrt(wx * wx + wy * wy);
-    const R fw = (wsv <= (R)40) ? m_exp((R)0.05039 * wsv)
-                                : (R)12 * -m_expm1((R)-0.0818 * (wsv - (R)28));
+    // exp(0.05039 WSV) is f(W) up to 40 km/h, and its reciprocal is the back
+    // fire's wind function at every speed
+    const R ew = m_exp((R)0.05039 * wsv);
+    const R fw = (wsv <= (R)40) ? ew : (R)12 * -m_expm1((R)-0.0818 * (wsv - (R)28));
     const R be = row[kRowBE + f];
     const R isz = row[1];
     CellRates<R> out;
     out.h = rsi_fuel(coef, f, isz * fw, L) * be;
-    out.b = rsi_fuel(coef, f, isz * m_exp((R)-0.05039 * wsv), L) * be;
+    out.b = rsi_fuel(coef, f, isz * recip(ew), L) * be;
     // LB - 1: grass 1.1 WSV^0.464 - 1 (0 below 1 km/h), other fuels
     // 8.729 (1 - exp(-0.030 WSV))^2.155, as one power per lane
     const bool grass = f >= kO1a;

@@ -123,16 +123,29 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
         int32_t q[8];
         axis_q<R>(X, rec, c, (uint32_t)p, q);
         evals = 1;
-        const int64_t n = (int64_t)(e - m0 + 1);
+        // minutes left in p; metres left per axis are below 2^16 (at most
+        // the diagonal of a 20 km cell), so when q < r and n < r every
+        // product below fits in 32 bits
+        const int32_t n = e - m0 + 1;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if (!((live >> k) & 1u)) continue;
-            const int32_t qk = q[k];
-            if (qk > 0 && (int64_t)qk * n >= rem[k]) {
-                cand[k] = m0 + (rem[k] + qk - 1) / qk - 1;
+            const int32_t qk = q[k], r = rem[k];
+            bool reach = false;
+            int32_t step = 0;
+            if (qk > 0) {
+                if (qk >= r || n >= r) {
+                    reach = true;
+                } else {
+                    step = qk * n;
+                    reach = step >= r;
+                }
+            }
+            if (reach) {
+                cand[k] = m0 + ceil_div_small(r, qk, __builtin_amdgcn_rcpf((float)qk)) - 1;
                 rem[k] = 0;
             } else {
-                rem[k] -= (int32_t)((int64_t)qk * n);
+                rem[k] = r - step;
                 if ((settled >> k) & 1u) rem[k] = 0;   // nothing after p can beat it
             }
         }
@@ -207,6 +220,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         const int32_t D[8] = {job.d_orth, job.d_diag, job.d_orth, job.d_diag,
                               job.d_orth, job.d_diag, job.d_orth, job.d_diag};
         const int32_t off[8] = {1, 1 - cols, -cols, -cols - 1, -1, cols - 1, cols, cols + 1};
+        const int64_t last_cell = (int64_t)rows * cols - 1;
 
         // ------------------------------------------- replication set-up
         if (tid == 0) {
@@ -336,19 +350,17 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                 rec.info = 0;
                 if (act) {
                     // issue every load of the entry at once: own label,
-                    // cell record and the labels of the in-grid neighbours
+                    // cell record and the labels of the 8 neighbours.  A
+                    // neighbour outside the grid is read at an index clamped
+                    // into the plane and never used: the record's neighbour
+                    // mask (in-grid burnable cells) excludes its axis.
                     const uint32_t own = load_label(&plane[c]);
                     rec = cells[c];
-                    const int r = (int)(c / (uint32_t)cols), col = (int)(c - (uint32_t)r * (uint32_t)cols);
-                    // axes E NE N NW W SW S SE = bits 0..7; drop those leaving the grid
-                    uint32_t inb = 0xFFu;
-                    if (col + 1 >= cols) inb &= ~0x83u;   // E, NE, SE
-                    if (col == 0) inb &= ~0x38u;          // NW, W, SW
-                    if (r == 0) inb &= ~0x0Eu;            // NE, N, NW
-                    if (r + 1 >= rows) inb &= ~0xE0u;     // SW, S, SE
 #pragma unroll
-                    for (int k = 0; k < 8; ++k)
-                        nbv[k] = ((inb >> k) & 1u) ? plane[(int64_t)c + off[k]] : kPlaneFill;
+                    for (int k = 0; k < 8; ++k) {
+                        const int64_t j = (int64_t)c + off[k];
+                        nbv[k] = plane[j < 0 ? 0 : (j > last_cell ? last_cell : j)];
+                    }
                     act = own == lab;
                 }
                 bool keep = false;
