@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libc2f.so")
 SOURCES = ["prep.hip", "propagate.hip", "split.hip", "order.hip", "capi.cpp"]
-HEADERS = ["device.h", "fuel_table.h", "kernels.h", "ln64.h", "small_div.h", "types.h"]
+HEADERS = ["device.h", "fuel_table.h", "kernels.h", "ln64.h", "types.h"]
 
 HIPCC_FLAGS = [
     "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",

@@ -8,7 +8,6 @@
 
 #include "fuel_table.h"
 #include "ln64.h"
-#include "small_div.h"
 #include "types.h"
 
 namespace c2f {

@@ -142,7 +142,7 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
                 }
             }
             if (reach) {
-                cand[k] = m0 + ceil_div_small(r, qk, __builtin_amdgcn_rcpf((float)qk)) - 1;
+                cand[k] = m0 + (r + qk - 1) / qk - 1;
                 rem[k] = 0;
             } else {
                 rem[k] = r - step;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         const int32_t D[8] = {job.d_orth, job.d_diag, job.d_orth, job.d_diag,
                               job.d_orth, job.d_diag, job.d_orth, job.d_diag};
         const int32_t off[8] = {1, 1 - cols, -cols, -cols - 1, -1, cols - 1, cols, cols + 1};
-        const int64_t last_cell = (int64_t)rows * cols - 1;
+        const uint32_t last_cell = (uint32_t)((int64_t)rows * cols - 1);
 
         // ------------------------------------------- replication set-up
         if (tid == 0) {
@@ -352,15 +352,14 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                     // issue every load of the entry at once: own label,
                     // cell record and the labels of the 8 neighbours.  A
                     // neighbour outside the grid is read at an index clamped
-                    // into the plane and never used: the record's neighbour
-                    // mask (in-grid burnable cells) excludes its axis.
+                    // into the plane (an index below 0 wraps to a large
+                    // unsigned value and clamps too) and never used: the
+                    // record's neighbour mask (in-grid burnable cells)
+                    // excludes its axis.  Grids hold fewer than 2^31 cells.
                     const uint32_t own = load_label(&plane[c]);
                     rec = cells[c];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int64_t j = (int64_t)c + off[k];
-                        nbv[k] = plane[j < 0 ? 0 : (j > last_cell ? last_cell : j)];
-                    }
+                    for (int k = 0; k < 8; ++k) nbv[k] = plane[min(c + (uint32_t)off[k], last_cell)];
                     act = own == lab;
                 }
                 bool keep = false;
