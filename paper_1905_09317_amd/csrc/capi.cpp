@@ -94,6 +94,11 @@ struct Exec {
     uint32_t* planes = nullptr;   // n_slots x plane_cells arrival labels
     int64_t plane_cells = 0;
     int32_t n_slots = 0;
+    // Serving lanes hold one plane pool and lay the slots out inside it per
+    // launch (plane_cells = the launch's rounded grid size); the first
+    // tag_ready slots hold planes and tags valid for that layout.
+    size_t plane_pool = 0;
+    int32_t tag_ready = 0;
     uint8_t* lists = nullptr;     // list_slots x list_cap x kSlotListBytesPerEntry
     int64_t list_cap = 0;
     int32_t list_slots = 0;
@@ -109,6 +114,8 @@ struct Exec {
 
     void* staging = nullptr;          // device copy of host-bound outputs
     size_t staging_bytes = 0;
+    void* host_stage = nullptr;       // pinned host copy of the same, read by memcpy
+    size_t host_stage_bytes = 0;
     int2* item_slot = nullptr;        // {slot, tag} per item of a launch
     int32_t item_slot_cap = 0;
     unsigned long long* order_keys = nullptr;   // replication order: a key
@@ -159,6 +166,7 @@ struct c2f_ctx {
     int device = 0;
     uint64_t budget = 0;        // caller's cap on device bytes (0 = none)
     uint64_t admit_limit = 0;   // bytes serving admission plans against
+    size_t lane_plane_budget = 0;   // plane pool of one serving lane
     int n_cu = 0;
     std::chrono::steady_clock::time_point t0;
 
@@ -317,7 +325,7 @@ c2f_status exec_init(c2f_ctx* ctx, Exec& ex, bool lane) {
 void exec_trim(c2f_ctx* ctx, Exec& ex) {
     if (ex.stream) (void)hipStreamSynchronize(ex.stream);
     drop_graph(ex);
-    dev_free(ctx, ex.planes, (size_t)ex.n_slots * ex.plane_cells * 4);
+    dev_free(ctx, ex.planes, ex.round_up ? ex.plane_pool : (size_t)ex.n_slots * ex.plane_cells * 4);
     dev_free(ctx, ex.lists, (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry);
     dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
     dev_free(ctx, ex.staging, ex.staging_bytes);
@@ -340,6 +348,11 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     ex.planes = nullptr;
     ex.n_slots = 0;
     ex.plane_cells = 0;
+    ex.plane_pool = 0;
+    ex.tag_ready = 0;
+    if (ex.host_stage) (void)hipHostFree(ex.host_stage);
+    ex.host_stage = nullptr;
+    ex.host_stage_bytes = 0;
     ex.lists = nullptr;
     ex.list_slots = 0;
     ex.list_cap = 0;
@@ -393,28 +406,87 @@ SlotSizes slot_sizes(const Exec& ex, int32_t n, int64_t cells, int64_t cap) {
     return s;
 }
 
+// Plane pool a serving lane allocates to run n slots of `cells`: the lane's
+// share of the serving memory, or more when a single launch needs it.
+size_t lane_pool_bytes(size_t budget, int32_t n, int64_t cells) {
+    return std::max(budget, (size_t)n * (size_t)pow2_at_least(cells) * 4);
+}
+
+// Slots a serving lane runs for grids of `cells`: as many as its plane pool
+// holds (at least one).
+int32_t lane_slot_cap(size_t budget, int64_t cells) {
+    const size_t per = (size_t)pow2_at_least(cells) * 4;
+    return (int32_t)std::max<size_t>(1, std::min<size_t>(budget / per, (size_t)1 << 20));
+}
+
 // Device bytes `ex` would add to run n slots of `cells` with lists of
-// `cap` entries, `stage` bytes of output staging and n_jobs requests.
-size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t stage, int32_t n_jobs) {
+// `cap` entries, `stage` bytes of output staging and n_jobs requests
+// (`budget`: a serving lane's plane pool).
+size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t stage, int32_t n_jobs,
+                   size_t budget) {
     const SlotSizes s = slot_sizes(ex, n, cells, cap);
     size_t g = 0;
     if (n_jobs > ex.d_jobs_cap)
         g += ((size_t)pow2_at_least(std::max(n_jobs, 64)) - (size_t)ex.d_jobs_cap) * sizeof(Job);
-    if (s.grow_planes) {
+    if (ex.round_up) {
+        const size_t need = (size_t)n * (size_t)pow2_at_least(cells) * 4;
+        if (need > ex.plane_pool) g += lane_pool_bytes(budget, n, cells) - ex.plane_pool;
+        if (n > ex.tag_slots) g += ((size_t)pow2_at_least(n) - (size_t)ex.tag_slots) * 4;
+    } else if (s.grow_planes) {
         g += (size_t)s.n_slots * s.plane_cells * 4 - (size_t)ex.n_slots * ex.plane_cells * 4;
         g += (size_t)s.n_slots * 4;
     }
     if (s.grow_lists)
         g += (size_t)s.list_slots * s.list_cap * kSlotListBytesPerEntry -
              (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry;
-    if (stage > ex.staging_bytes) g += stage - ex.staging_bytes;
+    const size_t stage_alloc = ex.round_up && stage ? (size_t)pow2_at_least((int64_t)stage) : stage;
+    if (stage_alloc > ex.staging_bytes) g += stage_alloc - ex.staging_bytes;
     if (n > ex.item_slot_cap) g += ((size_t)pow2_at_least(std::max(n, 64)) - (size_t)ex.item_slot_cap) * sizeof(int2);
     return g;
 }
 
 c2f_status ensure_slots(c2f_ctx* ctx, Exec& ex, int32_t n, int64_t cells, int64_t cap) {
     const SlotSizes s = slot_sizes(ex, n, cells, cap);
-    if (s.grow_planes) {
+    if (ex.round_up) {
+        // Serving lane: one plane pool, allocated once (or when a single
+        // launch needs more); slots are laid out at the launch's rounded
+        // grid size, and a slot whose plane holds another layout's labels
+        // starts from an exhausted tag, so that its work group refills the
+        // plane before its first replication.
+        const int64_t stride = pow2_at_least(cells);
+        const size_t need = (size_t)n * (size_t)stride * 4;
+        if (need > ex.plane_pool) {
+            drop_graph(ex);
+            dev_free(ctx, ex.planes, ex.plane_pool);
+            ex.planes = nullptr;
+            ex.plane_pool = 0;
+            ex.tag_ready = 0;
+            const size_t pool = lane_pool_bytes(ctx->lane_plane_budget, n, cells);
+            c2f_status st = dev_alloc(ctx, (void**)&ex.planes, pool);
+            if (st != C2F_OK) return st;
+            ex.plane_pool = pool;
+        }
+        if (n > ex.tag_slots) {
+            drop_graph(ex);
+            dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
+            ex.tags = nullptr;
+            ex.tag_slots = 0;
+            ex.tag_ready = 0;
+            const int32_t nt = (int32_t)pow2_at_least(n);
+            c2f_status st = dev_alloc(ctx, (void**)&ex.tags, (size_t)nt * 4);
+            if (st != C2F_OK) return st;
+            ex.tag_slots = nt;
+        }
+        if (stride != ex.plane_cells) {
+            ex.plane_cells = stride;
+            ex.tag_ready = 0;
+        }
+        if (n > ex.tag_ready) {
+            HIP_TRY(ctx, launch_fill_u32(ex.tags + ex.tag_ready, (size_t)(n - ex.tag_ready), 0u, ex.stream));
+            ex.tag_ready = n;
+        }
+        ex.n_slots = std::max(ex.n_slots, n);
+    } else if (s.grow_planes) {
         drop_graph(ex);
         dev_free(ctx, ex.planes, (size_t)ex.n_slots * ex.plane_cells * 4);
         ex.planes = nullptr;
@@ -536,9 +608,30 @@ c2f_status ensure_staging(c2f_ctx* ctx, Exec& ex, size_t bytes) {
         dev_free(ctx, ex.staging, ex.staging_bytes);
         ex.staging = nullptr;
         ex.staging_bytes = 0;
-        c2f_status st = dev_alloc(ctx, &ex.staging, bytes);
+        const size_t alloc = ex.round_up ? (size_t)pow2_at_least((int64_t)bytes) : bytes;
+        c2f_status st = dev_alloc(ctx, &ex.staging, alloc);
         if (st != C2F_OK) return st;
-        ex.staging_bytes = bytes;
+        ex.staging_bytes = alloc;
+    }
+    return C2F_OK;
+}
+
+// Pinned host memory the device staging is copied into in one transfer;
+// the host then copies each output to the caller's (possibly pageable)
+// buffer.  A device-to-pageable copy goes through the runtime's own bounce
+// buffer in pieces and serialises concurrent lanes.
+c2f_status ensure_host_stage(c2f_ctx* ctx, Exec& ex, size_t bytes) {
+    if (bytes > ex.host_stage_bytes) {
+        if (ex.host_stage) (void)hipHostFree(ex.host_stage);
+        ex.host_stage = nullptr;
+        ex.host_stage_bytes = 0;
+        const size_t alloc = ex.round_up ? (size_t)pow2_at_least((int64_t)bytes) : bytes;
+        if (hipHostMalloc(&ex.host_stage, alloc, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ex.host_stage = nullptr;
+            return fail(ctx, C2F_ENOMEM, "pinned host staging of %zu bytes failed", alloc);
+        }
+        ex.host_stage_bytes = alloc;
     }
     return C2F_OK;
 }
@@ -635,6 +728,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
         total += P[k].reps;
     }
     LaunchPlan lp = plan_launch(ctx, max_cells, total, precision, grid_cap);
+    if (ex.round_up) lp.grid = std::min(lp.grid, lane_slot_cap(ctx->lane_plane_budget, max_cells));
     c2f_status st = ensure_jobs(ctx, ex, (int32_t)idx.size());
     if (st != C2F_OK) return st;
     bool dense = false;
@@ -916,24 +1010,30 @@ c2f_status run_requests(c2f_ctx* ctx, Exec& ex, const std::vector<c2f_sim_params
     st = run_group(ctx, ex, g32, P, Ls, Ws, plans, 1, use_graph, grid_cap);
     if (st != C2F_OK) return st;
 
-    // copy host outputs back
+    // copy host outputs back: the whole staging area in one transfer to
+    // pinned memory, then each output to the caller's buffer
+    if (stage > 0) {
+        st = ensure_host_stage(ctx, ex, stage);
+        if (st != C2F_OK) return st;
+        HIP_TRY(ctx, hipMemcpyAsync(ex.host_stage, ex.staging, stage, hipMemcpyDeviceToHost, ex.stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
+    const char* hb = (const char*)ex.host_stage;
     for (int k = 0; k < n_jobs; ++k) {
         const c2f_outputs& o = outs[k];
         if (o.on_device) continue;
         const size_t n = (size_t)Ls[k]->ncells(), r = (size_t)P[k].reps;
-        auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
-            if (!dst) return hipSuccess;
-            return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ex.stream);
+        auto cp = [&](void* dst, size_t off, size_t bytes) {
+            if (dst && off) memcpy(dst, hb + off - 1, bytes);
         };
-        HIP_TRY(ctx, cp(o.scar, plans[k].scar, r * n));
-        HIP_TRY(ctx, cp(o.arrival_period, plans[k].arr_period, r * n * 4));
-        HIP_TRY(ctx, cp(o.arrival_minute, plans[k].arr_minute, r * n * 4));
-        HIP_TRY(ctx, cp(o.burn_count, plans[k].count, n * 4));
-        HIP_TRY(ctx, cp(o.burned_cells, plans[k].burned, r * 8));
-        HIP_TRY(ctx, cp(o.ignition_cell, plans[k].ign, r * 4));
-        HIP_TRY(ctx, cp(o.scenario, plans[k].scen, r * 4));
+        cp(o.scar, offs[k][0], r * n);
+        cp(o.arrival_period, offs[k][1], r * n * 4);
+        cp(o.arrival_minute, offs[k][2], r * n * 4);
+        cp(o.burn_count, offs[k][3], n * 4);
+        cp(o.burned_cells, offs[k][4], r * 8);
+        cp(o.ignition_cell, offs[k][5], r * 4);
+        cp(o.scenario, offs[k][6], r * 4);
     }
-    HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
     return C2F_OK;
 }
 
@@ -974,15 +1074,20 @@ size_t batch_growth(c2f_ctx* ctx, const Exec& ex, const std::vector<std::shared_
     for (int pr = 0; pr < 2; ++pr) {
         if (!items[pr]) continue;
         const LaunchPlan lp = plan_launch(ctx, cells[pr], items[pr], pr, ctx->max_batch_grid);
-        grid = std::max(grid, lp.grid);
+        grid = std::max(grid, std::min(lp.grid, lane_slot_cap(ctx->lane_plane_budget, cells[pr])));
         cap = std::max(cap, lp.cap);
         max_cells = std::max(max_cells, cells[pr]);
     }
-    size_t g = exec_growth(ex, grid, max_cells, cap, stage, (int32_t)batch.size());
+    size_t g = exec_growth(ex, grid, max_cells, cap, stage, (int32_t)batch.size(), ctx->lane_plane_budget);
     const int32_t n_items = std::max(items[0], items[1]);
     if (n_items > grid && n_items > ex.order_cap)   // a launch in replication order
         g += ((size_t)pow2_at_least(std::max(n_items, 64)) - (size_t)ex.order_cap) * kOrderBytesPerItem;
-    if (batch.size() == 1 && max_cells > ex.rate_cache_cells)   // a possible period-split launch
+    bool split_possible;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tunemu);
+        split_possible = ctx->split_mode == 2;
+    }
+    if (split_possible && batch.size() == 1 && max_cells > ex.rate_cache_cells)   // a possible period-split launch
         g += (size_t)((ex.round_up ? pow2_at_least(max_cells) : max_cells) - ex.rate_cache_cells) * sizeof(uint4);
     return g;
 }
@@ -1122,6 +1227,13 @@ void lane_loop(c2f_ctx* ctx, Lane* ln) {
 // Start the serving lanes (caller holds smu).
 c2f_status start_lanes(c2f_ctx* ctx) {
     if (!ctx->lanes.empty()) return C2F_OK;
+    // each lane's plane pool: a share of the admission memory left beside
+    // the resident inputs (half of it split over the lanes), at most 16 GiB
+    {
+        const size_t held = bytes_in_use(ctx);
+        const size_t avail = ctx->admit_limit > held ? (size_t)ctx->admit_limit - held : 0;
+        ctx->lane_plane_budget = std::min<size_t>((size_t)16 << 30, avail / (2 * (size_t)std::max(1, ctx->n_lanes)));
+    }
     for (int32_t i = 0; i < ctx->n_lanes; ++i) {
         std::unique_ptr<Lane> ln(new Lane());
         ln->index = i;
