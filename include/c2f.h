@@ -263,7 +263,8 @@ c2f_status c2f_wait_info(c2f_ctx* ctx, uint64_t ticket, c2f_ticket_info* info);
 
 /* Serving configuration, before the first c2f_submit (ESTATE after):
  * lanes (1..16, default 4) concurrent batches; max_batch_reps (default
- * 65536) replications fused into one batch; max_batch_grid resident work
+ * 2048) replications fused into one batch (a batch also stops taking
+ * requests at 512 MiB of host-bound outputs); max_batch_grid resident work
  * groups one batch may use (0 = all that fit the device); admit_bytes the
  * device bytes admission plans against (0 = keep the default; at most the
  * context's budget). */

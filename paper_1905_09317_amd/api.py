@@ -226,7 +226,7 @@ class Simulator:
         return {k: getattr(s, k) for k, _ in RunStats._fields_}
 
     # ------------------------------------------------------------ serving
-    def set_serving(self, lanes: int = 4, max_batch_reps: int = 1 << 16, max_batch_grid: int = 0,
+    def set_serving(self, lanes: int = 4, max_batch_reps: int = 2048, max_batch_grid: int = 0,
                     admit_bytes: int = 0):
         """Serving lanes, batch limits and admission memory; call before the
         first submit."""

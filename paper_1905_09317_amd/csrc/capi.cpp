@@ -99,6 +99,7 @@ struct Exec {
     // tag_ready slots hold planes and tags valid for that layout.
     size_t plane_pool = 0;
     int32_t tag_ready = 0;
+    size_t list_pool = 0;         // serving lanes: bytes held for the lists, laid out per launch
     uint8_t* lists = nullptr;     // list_slots x list_cap x kSlotListBytesPerEntry
     int64_t list_cap = 0;
     int32_t list_slots = 0;
@@ -167,6 +168,7 @@ struct c2f_ctx {
     uint64_t budget = 0;        // caller's cap on device bytes (0 = none)
     uint64_t admit_limit = 0;   // bytes serving admission plans against
     size_t lane_plane_budget = 0;   // plane pool of one serving lane
+    size_t lane_list_budget = 0;    // list pool of one serving lane
     int n_cu = 0;
     std::chrono::steady_clock::time_point t0;
 
@@ -202,7 +204,7 @@ struct c2f_ctx {
     std::vector<std::unique_ptr<Lane>> lanes;
     int32_t n_lanes = 4;
     int32_t max_queue = 4096;
-    int32_t max_batch_reps = 1 << 16;
+    int32_t max_batch_reps = 2048;
     int32_t max_batch_grid = 0;
     int32_t busy_lanes = 0;
     size_t promised = 0;   // growth admitted to running lanes, not yet released
@@ -326,7 +328,8 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     if (ex.stream) (void)hipStreamSynchronize(ex.stream);
     drop_graph(ex);
     dev_free(ctx, ex.planes, ex.round_up ? ex.plane_pool : (size_t)ex.n_slots * ex.plane_cells * 4);
-    dev_free(ctx, ex.lists, (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry);
+    dev_free(ctx, ex.lists,
+             ex.round_up ? ex.list_pool : (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry);
     dev_free(ctx, ex.tags, (size_t)ex.tag_slots * 4);
     dev_free(ctx, ex.staging, ex.staging_bytes);
     dev_free(ctx, ex.d_jobs, (size_t)ex.d_jobs_cap * sizeof(Job));
@@ -350,6 +353,7 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     ex.plane_cells = 0;
     ex.plane_pool = 0;
     ex.tag_ready = 0;
+    ex.list_pool = 0;
     if (ex.host_stage) (void)hipHostFree(ex.host_stage);
     ex.host_stage = nullptr;
     ex.host_stage_bytes = 0;
@@ -419,11 +423,21 @@ int32_t lane_slot_cap(size_t budget, int64_t cells) {
     return (int32_t)std::max<size_t>(1, std::min<size_t>(budget / per, (size_t)1 << 20));
 }
 
+// List capacity a serving lane gives each of n slots: the launch's plan,
+// at most what its list pool holds (an overflow still relaunches larger).
+int64_t lane_list_cap(size_t list_budget, int32_t n, int64_t cap) {
+    int64_t fit = (int64_t)(list_budget / ((size_t)std::max(n, 1) * kSlotListBytesPerEntry));
+    fit = std::max<int64_t>(fit, 4096);
+    int64_t c = pow2_at_least(cap);
+    while (c > fit && c > 4096) c >>= 1;
+    return c;
+}
+
 // Device bytes `ex` would add to run n slots of `cells` with lists of
 // `cap` entries, `stage` bytes of output staging and n_jobs requests
-// (`budget`: a serving lane's plane pool).
+// (`budget`, `list_budget`: a serving lane's plane and list pools).
 size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t stage, int32_t n_jobs,
-                   size_t budget) {
+                   size_t budget, size_t list_budget) {
     const SlotSizes s = slot_sizes(ex, n, cells, cap);
     size_t g = 0;
     if (n_jobs > ex.d_jobs_cap)
@@ -432,11 +446,13 @@ size_t exec_growth(const Exec& ex, int32_t n, int64_t cells, int64_t cap, size_t
         const size_t need = (size_t)n * (size_t)pow2_at_least(cells) * 4;
         if (need > ex.plane_pool) g += lane_pool_bytes(budget, n, cells) - ex.plane_pool;
         if (n > ex.tag_slots) g += ((size_t)pow2_at_least(n) - (size_t)ex.tag_slots) * 4;
+        const size_t lneed = (size_t)n * (size_t)pow2_at_least(cap) * kSlotListBytesPerEntry;
+        if (lneed > ex.list_pool) g += std::max(lneed, list_budget) - ex.list_pool;
     } else if (s.grow_planes) {
         g += (size_t)s.n_slots * s.plane_cells * 4 - (size_t)ex.n_slots * ex.plane_cells * 4;
         g += (size_t)s.n_slots * 4;
     }
-    if (s.grow_lists)
+    if (!ex.round_up && s.grow_lists)
         g += (size_t)s.list_slots * s.list_cap * kSlotListBytesPerEntry -
              (size_t)ex.list_slots * ex.list_cap * kSlotListBytesPerEntry;
     const size_t stage_alloc = ex.round_up && stage ? (size_t)pow2_at_least((int64_t)stage) : stage;
@@ -486,6 +502,23 @@ c2f_status ensure_slots(c2f_ctx* ctx, Exec& ex, int32_t n, int64_t cells, int64_
             ex.tag_ready = n;
         }
         ex.n_slots = std::max(ex.n_slots, n);
+        // lists: one pool as well, laid out per launch (they need no
+        // initial contents)
+        const int64_t lcap = pow2_at_least(cap);
+        const size_t lneed = (size_t)n * (size_t)lcap * kSlotListBytesPerEntry;
+        if (lneed > ex.list_pool) {
+            drop_graph(ex);
+            dev_free(ctx, ex.lists, ex.list_pool);
+            ex.lists = nullptr;
+            ex.list_pool = 0;
+            const size_t pool = std::max(lneed, ctx->lane_list_budget);
+            c2f_status st = dev_alloc(ctx, (void**)&ex.lists, pool);
+            if (st != C2F_OK) return st;
+            ex.list_pool = pool;
+        }
+        ex.list_cap = lcap;
+        ex.list_slots = n;
+        return C2F_OK;
     } else if (s.grow_planes) {
         drop_graph(ex);
         dev_free(ctx, ex.planes, (size_t)ex.n_slots * ex.plane_cells * 4);
@@ -728,7 +761,10 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
         total += P[k].reps;
     }
     LaunchPlan lp = plan_launch(ctx, max_cells, total, precision, grid_cap);
-    if (ex.round_up) lp.grid = std::min(lp.grid, lane_slot_cap(ctx->lane_plane_budget, max_cells));
+    if (ex.round_up) {
+        lp.grid = std::min(lp.grid, lane_slot_cap(ctx->lane_plane_budget, max_cells));
+        lp.cap = lane_list_cap(std::max(ctx->lane_list_budget, ex.list_pool), lp.grid, lp.cap);
+    }
     c2f_status st = ensure_jobs(ctx, ex, (int32_t)idx.size());
     if (st != C2F_OK) return st;
     bool dense = false;
@@ -1078,7 +1114,8 @@ size_t batch_growth(c2f_ctx* ctx, const Exec& ex, const std::vector<std::shared_
         cap = std::max(cap, lp.cap);
         max_cells = std::max(max_cells, cells[pr]);
     }
-    size_t g = exec_growth(ex, grid, max_cells, cap, stage, (int32_t)batch.size(), ctx->lane_plane_budget);
+    size_t g = exec_growth(ex, grid, max_cells, lane_list_cap(std::max(ctx->lane_list_budget, ex.list_pool), grid, cap), stage,
+                           (int32_t)batch.size(), ctx->lane_plane_budget, ctx->lane_list_budget);
     const int32_t n_items = std::max(items[0], items[1]);
     if (n_items > grid && n_items > ex.order_cap)   // a launch in replication order
         g += ((size_t)pow2_at_least(std::max(n_items, 64)) - (size_t)ex.order_cap) * kOrderBytesPerItem;
@@ -1100,14 +1137,23 @@ bool fits(c2f_ctx* ctx, size_t growth) {
 // smu).  Requests are taken in arrival order while the lane's added device
 // memory fits the admission limit; a head that does not fit waits for
 // running lanes, and idle lanes give back their buffers to make room.
+// Host-bound output bytes a batch collects before it stops taking requests
+// (a single larger request still runs): keeps the lanes' staging buffers
+// from growing, and each batch's results from waiting on a long transfer.
+constexpr size_t kBatchHostBytes = (size_t)512 << 20;
+
 bool try_admit(c2f_ctx* ctx, Lane& ln, std::vector<std::shared_ptr<Ticket>>& batch, size_t& growth) {
     batch.clear();
     growth = 0;
     if (ctx->queue.empty()) return false;
     int64_t items = 0;
+    size_t host_bytes = 0;
     for (auto it = ctx->queue.begin(); it != ctx->queue.end(); ++it) {
         const auto& t = *it;
         if (!batch.empty() && items + t->params.reps > ctx->max_batch_reps) break;
+        const size_t hb = host_output_bytes(t->out, t->L->ncells(), t->params.reps);
+        if (!batch.empty() && host_bytes + hb > kBatchHostBytes) break;
+        host_bytes += hb;
         batch.push_back(t);
         const size_t g = batch_growth(ctx, ln.ex, batch);
         if (!fits(ctx, g)) {
@@ -1224,20 +1270,54 @@ void lane_loop(c2f_ctx* ctx, Lane* ln) {
     }
 }
 
+// A lane's long-lived buffers, taken when serving starts rather than in
+// the middle of a stream, where an allocation of many GB stalls for a
+// second and a free waits for the whole device: the plane pool, and
+// output staging (device and pinned host) for a batch's host-bound
+// outputs, each within the lane's share of the serving memory.
+c2f_status lane_reserve(c2f_ctx* ctx, Exec& ex) {
+    const size_t budget = ctx->lane_plane_budget;
+    if (budget >= ((size_t)64 << 20) && !ex.planes) {
+        c2f_status st = dev_alloc(ctx, (void**)&ex.planes, budget);
+        if (st != C2F_OK) return st;
+        ex.plane_pool = budget;
+        ex.plane_cells = 0;
+        ex.tag_ready = 0;
+    }
+    if (ctx->lane_list_budget >= ((size_t)16 << 20) && !ex.lists) {
+        c2f_status st = dev_alloc(ctx, (void**)&ex.lists, ctx->lane_list_budget);
+        if (st != C2F_OK) return st;
+        ex.list_pool = ctx->lane_list_budget;
+        ex.list_cap = 0;
+        ex.list_slots = 0;
+    }
+    const size_t stage = std::min(kBatchHostBytes, budget / 8);
+    if (stage >= ((size_t)1 << 20)) {
+        c2f_status st = ensure_staging(ctx, ex, stage);
+        if (st == C2F_OK) st = ensure_host_stage(ctx, ex, stage);
+        if (st != C2F_OK) return st;
+    }
+    return C2F_OK;
+}
+
 // Start the serving lanes (caller holds smu).
 c2f_status start_lanes(c2f_ctx* ctx) {
     if (!ctx->lanes.empty()) return C2F_OK;
-    // each lane's plane pool: a share of the admission memory left beside
-    // the resident inputs (half of it split over the lanes), at most 16 GiB
+    // each lane's pools: a share of the admission memory left beside the
+    // resident inputs (half of it split over the lanes, at most 20 GiB),
+    // three quarters for planes and one for lists
     {
         const size_t held = bytes_in_use(ctx);
         const size_t avail = ctx->admit_limit > held ? (size_t)ctx->admit_limit - held : 0;
-        ctx->lane_plane_budget = std::min<size_t>((size_t)16 << 30, avail / (2 * (size_t)std::max(1, ctx->n_lanes)));
+        const size_t share = std::min<size_t>((size_t)20 << 30, avail / (2 * (size_t)std::max(1, ctx->n_lanes)));
+        ctx->lane_plane_budget = share / 4 * 3;
+        ctx->lane_list_budget = share / 4;
     }
     for (int32_t i = 0; i < ctx->n_lanes; ++i) {
         std::unique_ptr<Lane> ln(new Lane());
         ln->index = i;
         c2f_status st = exec_init(ctx, ln->ex, true);
+        if (st == C2F_OK) st = lane_reserve(ctx, ln->ex);
         if (st != C2F_OK) {
             exec_release(ctx, ln->ex);
             for (auto& l : ctx->lanes) exec_release(ctx, l->ex);
