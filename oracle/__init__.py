@@ -51,8 +51,11 @@ def _load():
         L.oracle_simulate.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
                                       i32, i32, i32, u64, f64, f64, i32, i32, i32, i32, i32,
                                       i32, P, P, P, P, P, P, P, P, P, P]
+        L.oracle_simulate_ext.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
+                                          i32, i32, i32, u64, f64, f64, i32, i32, i32, P, i32, i32,
+                                          i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_eval_ros_cells",
-                   "oracle_simulate"):
+                   "oracle_simulate", "oracle_simulate_ext"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -145,10 +148,14 @@ def eval_ros(fuel, elev, weather, *, cell_m=100, scenario=0, period=0, rep=0, se
 def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0, seed=0,
              sigma=0.0, threshold=0.0, rounding=0, ignition_mode=0, ignition_cell=0,
              scenario_mode=0, scenario=0, period_min=60, pc=50.0, curing=80.0,
-             overrides=None, want_rep_outputs=True) -> dict:
+             overrides=None, want_rep_outputs=True, ignition_weights=None, ignition_period=0,
+             burn_hours=0) -> dict:
     """Run the minute-stepping reference simulation.
 
     overrides: optional (keys int32 [n,3] of (rep, period, cell), q int32 [n,8]).
+    ignition_mode 3 draws the ignition from ignition_weights (uint32 per
+    cell); ignition_period starts the fire at that period; burn_hours (1..24)
+    is the daily burning window (0 = always).
     Returns scar/arrival_period/arrival_minute [reps, rows*cols] (if wanted),
     burn_count [rows*cols], burned_cells/ignition_cell/scenario [reps], stats [3].
     """
@@ -170,14 +177,20 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
         ok = np.ascontiguousarray(overrides[0], dtype=np.int32).reshape(-1, 3)
         oq = np.ascontiguousarray(overrides[1], dtype=np.int32).reshape(-1, 8)
         n_ov = ok.shape[0]
-    rc = _load().oracle_simulate(
+    iw = None
+    if ignition_weights is not None:
+        iw = np.ascontiguousarray(ignition_weights, dtype=np.uint32).reshape(-1)
+        if iw.size != n:
+            raise ValueError("ignition_weights must hold one weight per cell")
+    rc = _load().oracle_simulate_ext(
         rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc), float(curing), w.shape[0],
         w.shape[1], int(period_min), _ptr(w), int(reps), int(rep_offset), int(n_periods),
         int(seed) & (2**64 - 1), float(sigma), float(threshold), int(rounding),
-        int(ignition_mode), int(ignition_cell), int(scenario_mode), int(scenario), n_ov,
+        int(ignition_mode), int(ignition_cell), _ptr(iw), int(ignition_period), int(burn_hours),
+        int(scenario_mode), int(scenario), n_ov,
         _ptr(ok), _ptr(oq), _ptr(res.get("scar")), _ptr(res.get("arrival_period")),
         _ptr(res.get("arrival_minute")), _ptr(res["burn_count"]), _ptr(res["burned_cells"]),
         _ptr(res["ignition_cell"]), _ptr(res["scenario"]), _ptr(res["stats"]))
     if rc != 0:
-        raise ValueError("oracle_simulate: bad input")
+        raise ValueError("oracle_simulate_ext: bad input")
     return res

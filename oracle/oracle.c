@@ -485,14 +485,44 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
                     uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
                     int32_t* scenario_out, int64_t* stats) {
+    return oracle_simulate_ext(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
+                               period_min, weather, reps, rep_offset, n_periods, seed, sigma, threshold,
+                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, scenario_mode,
+                               scenario_fixed, n_override, override_key, override_q, scar, arrival_period,
+                               arrival_minute, burn_count, burned_cells, ignition_out, scenario_out, stats);
+}
+
+/* Is minute m (1-based) inside the daily burning window: the first
+ * burn_hours hours of every 24 h counted from the start of the run
+ * (assumption A5, general fire dynamics (1)); burn_hours 0 = every minute. */
+static int burning_minute(int32_t m, int32_t burn_hours) {
+    if (burn_hours <= 0) return 1;
+    return ((m - 1) % 1440) < burn_hours * 60;
+}
+
+int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
+                        const int16_t* elev, double pc_pct, double curing_pct,
+                        int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,
+                        int32_t reps, int32_t rep_offset, int32_t n_periods, uint64_t seed,
+                        double sigma, double threshold, int32_t rounding,
+                        int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
+                        int32_t ignition_period, int32_t burn_hours,
+                        int32_t scenario_mode, int32_t scenario_fixed,
+                        int32_t n_override, const int32_t* override_key, const int32_t* override_q,
+                        uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
+                        uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
+                        int32_t* scenario_out, int64_t* stats) {
     if (check_land(rows, cols, cell_m, fuel, pc_pct, curing_pct, n_scen, n_wperiods, weather)) return -1;
     if (reps <= 0 || rep_offset < 0 || n_periods <= 0 || n_periods > n_wperiods || period_min <= 0)
         return -1;
     if ((int64_t)n_periods * period_min > 0x7FFFFFF0ll) return -1;
     if (!(sigma >= 0.0) || !isfinite(threshold) || (rounding != 0 && rounding != 1)) return -1;
     const int64_t n = (int64_t)rows * cols;
-    if (ignition_mode < 0 || ignition_mode > 2) return -1;
+    if (ignition_mode < 0 || ignition_mode > 3) return -1;
     if (ignition_mode == 0 && (ignition_cell < 0 || ignition_cell >= n)) return -1;
+    if (ignition_mode == 3 && !ignition_weights) return -1;
+    if (ignition_period < 0 || ignition_period >= n_periods) return -1;
+    if (burn_hours < 0 || burn_hours > 24) return -1;
     if (scenario_mode < 0 || scenario_mode > 1) return -1;
     if (scenario_mode == 0 && (scenario_fixed < 0 || scenario_fixed >= n_scen)) return -1;
     if (n_override < 0 || (n_override > 0 && (!override_key || !override_q))) return -1;
@@ -551,6 +581,11 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
         }
     }
 
+    /* total ignition weight (spatial ignition map) */
+    uint64_t ign_total = 0;
+    if (ignition_mode == 3)
+        for (int64_t i = 0; i < n; ++i) ign_total += ignition_weights[i];
+
     int32_t* arrival = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     uint8_t* reached = (uint8_t*)malloc((size_t)n);
     int32_t* pending = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
@@ -576,22 +611,44 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                 draw(seed, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)rep, 3u, x);
                 ign = burnable[((uint64_t)x[0] * (uint64_t)n_burnable) >> 32];
             }
-        } else {
+        } else if (ignition_mode == 2) {
             ign = centre_cell;
+        } else {
+            /* spatial ignition probability (Section 3.1, uncertainty (1)):
+             * cell i with probability w_i / W.  The draw x (32 bits, tag 3)
+             * picks the target t = floor(x W / 2^32) in [0, W) and the
+             * ignition is the first cell whose running weight sum exceeds t. */
+            if (ign_total > 0) {
+                draw(seed, 0xFFFFFFFFu, 0xFFFFFFFFu, (uint32_t)rep, 3u, x);
+                const uint64_t t = (uint64_t)x[0] * (ign_total >> 32) +
+                                   (((uint64_t)x[0] * (ign_total & 0xFFFFFFFFull)) >> 32);
+                uint64_t run = 0;
+                for (int64_t i = 0; i < n; ++i) {
+                    run += ignition_weights[i];
+                    if (run > t) {
+                        ign = (int32_t)i;
+                        break;
+                    }
+                }
+            }
         }
         for (int64_t i = 0; i < n; ++i) arrival[i] = INF_T;
         memset(reached, 0, (size_t)n);
         size_t nb = 0, np = 0;
+        /* the ignition takes the last minute before its period */
+        const int32_t m0 = ignition_period * P;
         if (ign >= 0 && fuel[ign] != 0) {
-            arrival[ign] = 0;
+            arrival[ign] = m0;
             burn[0].cell = ign;
             burn[0].qperiod = -1;
             for (int k = 0; k < 8; ++k) burn[0].prog[k] = 0;
             nb = 1;
             ++st_ign;
         }
-        /* Step 2: fire dynamics, one clock minute at a time */
-        for (int32_t m = 1; m <= T && (nb > 0 || np > 0); ++m) {
+        /* Step 2: fire dynamics, one clock minute at a time; outside the
+         * daily burning window nothing spreads or ignites */
+        for (int32_t m = m0 + 1; m <= T && (nb > 0 || np > 0); ++m) {
+            if (!burning_minute(m, burn_hours)) continue;
             const int32_t p = (m - 1) / P;
             /* sending: every burning cell advances its fire along each axis
              * towards an available neighbour; reaching the neighbour's centre
