@@ -87,6 +87,16 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
                               float curing_pct, int32_t* landscape_id);
 c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id);
 
+/* Spatial ignition probability of a landscape (Section 3.1, uncertainty
+ * (1)): weights[rows*cols] (host, row-major, copied) give cell i the
+ * probability weights[i] / sum(weights) under ignition_mode 3.  The draw is
+ * integer: with x the 32-bit Philox word of tag 3 and W the sum, the target
+ * floor(x W / 2^32) selects the first cell whose running sum exceeds it.  A
+ * cell without fuel may be drawn and then burns nothing; an all-zero map
+ * ignites nothing.  weights == NULL removes the map.  EBUSY while the
+ * landscape is used by submitted requests. */
+c2f_status c2f_set_ignition_map(c2f_ctx* ctx, int32_t landscape_id, const uint32_t* weights);
+
 /* One weather record (Table WeatherT columns used by the FBP System):
  * FFMC (0..101), BUI (>= 0), wind speed km/h (>= 0) and the azimuth the
  * wind blows FROM, degrees clockwise from north. */
@@ -116,8 +126,20 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *                  1 = floor(x + u) with u uniform from Philox.
  *   precision      0 = FBP evaluated in FP64, 1 = in FP32.
  *   ignition_mode  0 = ignition_cell, 1 = uniform over burnable cells,
- *                  2 = the burnable cell nearest (rows/2, cols/2).
- *   scenario_mode  0 = scenario, 1 = uniform over the weather's scenarios. */
+ *                  2 = the burnable cell nearest (rows/2, cols/2),
+ *                  3 = drawn from the landscape's ignition map
+ *                  (c2f_set_ignition_map; Section 3.1, uncertainty (1)).
+ *   scenario_mode  0 = scenario, 1 = uniform over the weather's scenarios.
+ *   ignition_period  the fire is lit at the start of this period
+ *                  (0 <= ignition_period < n_periods): its cell takes minute
+ *                  ignition_period * period_min, and minute m belongs to
+ *                  period (m - 1) / period_min, so a later ignition reads as
+ *                  the period before it in arrival_period.
+ *   burn_hours     maximum burning hours per day (assumption A5): 0 or 24
+ *                  = no limit; 1..23 = fire spreads and cells ignite only
+ *                  in the first burn_hours hours of every day counted from
+ *                  the start of the run (progress pauses outside them).
+ *                  Needs a period length that divides 60 minutes. */
 typedef struct {
     int32_t landscape_id, weather_id, reps, n_periods;
     uint64_t seed;
@@ -126,6 +148,7 @@ typedef struct {
     int32_t ignition_mode, ignition_cell;
     int32_t scenario_mode, scenario;
     int32_t rep_offset;
+    int32_t ignition_period, burn_hours;
 } c2f_sim_params;
 
 /* Outputs of a simulation (Section 3.6 (i) burn grids and their counts).

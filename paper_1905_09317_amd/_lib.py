@@ -26,7 +26,8 @@ class SimParams(ctypes.Structure):
                 ("rounding", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("ignition_mode", ctypes.c_int32), ("ignition_cell", ctypes.c_int32),
                 ("scenario_mode", ctypes.c_int32), ("scenario", ctypes.c_int32),
-                ("rep_offset", ctypes.c_int32)]
+                ("rep_offset", ctypes.c_int32), ("ignition_period", ctypes.c_int32),
+                ("burn_hours", ctypes.c_int32)]
 
 
 class Outputs(ctypes.Structure):
@@ -97,6 +98,7 @@ def load() -> ctypes.CDLL:
         "c2f_get_memory": ([P, pp(u64), pp(u64)], i32),
         "c2f_set_period_split": ([P, i32], i32),
         "c2f_set_rep_order": ([P, i32], i32),
+        "c2f_set_ignition_map": ([P, i32, P], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -110,4 +112,5 @@ DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
             "c2f_simulate_batch", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
             "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
-            "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_period_split", "c2f_set_rep_order")
+            "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_period_split", "c2f_set_rep_order",
+            "c2f_set_ignition_map")

@@ -42,6 +42,8 @@ class Request:
     scenario_mode: int = 0
     scenario: int = 0
     rep_offset: int = 0
+    ignition_period: int = 0
+    burn_hours: int = 0
     outputs: tuple = OUTPUT_NAMES
     device_out: bool = False
 
@@ -49,7 +51,8 @@ class Request:
         return SimParams(self.landscape, self.weather, self.reps, self.n_periods,
                          int(self.seed) & (2**64 - 1), float(self.sigma), float(self.threshold),
                          self.rounding, self.precision, self.ignition_mode, self.ignition_cell,
-                         self.scenario_mode, self.scenario, self.rep_offset)
+                         self.scenario_mode, self.scenario, self.rep_offset, self.ignition_period,
+                         self.burn_hours)
 
 
 @dataclass
@@ -124,6 +127,19 @@ class Simulator:
     def unload_landscape(self, landscape: int):
         self._check(self._L.c2f_unload_landscape(self._ctx, int(landscape)))
         self._lands.pop(landscape, None)
+
+    def set_ignition_map(self, landscape: int, weights):
+        """Ignition probability per cell (ignition_mode 3): integer weights of
+        the landscape's shape; None removes the map."""
+        if weights is None:
+            self._check(self._L.c2f_set_ignition_map(self._ctx, int(landscape), None))
+            return
+        lm = self._lands[landscape]
+        w = np.ascontiguousarray(weights, dtype=np.uint32).reshape(-1)
+        if w.size != lm.rows * lm.cols:
+            raise ValueError(f"ignition map needs {lm.rows * lm.cols} weights, got {w.size}")
+        self._check(self._L.c2f_set_ignition_map(self._ctx, int(landscape),
+                                                 w.ctypes.data_as(ctypes.c_void_p)))
 
     def set_weather(self, weather, period_min: int = 60) -> int:
         w = np.ascontiguousarray(weather, dtype=np.float32)

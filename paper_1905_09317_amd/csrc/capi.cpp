@@ -43,6 +43,8 @@ struct Landscape {
     CellRec* cells = nullptr;
     int32_t* burnable = nullptr;
     LandDev* land = nullptr;
+    uint64_t* ign_cdf = nullptr;   // ignition map: running weight sums (device)
+    uint64_t ign_total = 0;
     int32_t inflight = 0;   // submitted requests not yet completed
     int64_t ncells() const { return (int64_t)rows * cols; }
 };
@@ -692,7 +694,15 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, Landscape** L, We
     if (!std::isfinite(p->ros_threshold)) return fail(ctx, C2F_EINVAL, "ros_threshold must be finite");
     if (p->rounding != 0 && p->rounding != 1) return fail(ctx, C2F_EINVAL, "rounding must be 0 or 1");
     if (p->precision != 0 && p->precision != 1) return fail(ctx, C2F_EINVAL, "precision must be 0 or 1");
-    if (p->ignition_mode < 0 || p->ignition_mode > 2) return fail(ctx, C2F_EINVAL, "ignition_mode must be 0..2");
+    if (p->ignition_mode < 0 || p->ignition_mode > 3) return fail(ctx, C2F_EINVAL, "ignition_mode must be 0..3");
+    if (p->ignition_mode == 3 && !l.ign_cdf)
+        return fail(ctx, C2F_EINVAL, "ignition_mode 3 needs an ignition map (c2f_set_ignition_map)");
+    if (p->ignition_period < 0 || p->ignition_period >= p->n_periods)
+        return fail(ctx, C2F_EINVAL, "ignition_period %d not in 0..%d", p->ignition_period, p->n_periods - 1);
+    if (p->burn_hours < 0 || p->burn_hours > 24) return fail(ctx, C2F_EINVAL, "burn_hours must be 0..24");
+    if (p->burn_hours > 0 && p->burn_hours < 24 && (w.period_min > 60 || 60 % w.period_min != 0))
+        return fail(ctx, C2F_EINVAL, "burn_hours needs a period length dividing 60 minutes (got %d)",
+                    w.period_min);
     if (p->ignition_mode == 0 && (p->ignition_cell < 0 || p->ignition_cell >= l.ncells()))
         return fail(ctx, C2F_EINVAL, "ignition_cell %d outside the grid", p->ignition_cell);
     if (p->scenario_mode < 0 || p->scenario_mode > 1) return fail(ctx, C2F_EINVAL, "scenario_mode must be 0 or 1");
@@ -784,6 +794,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     // persistent kernel (the hop chain waits on memory, not on the rate
     // evaluation), so it runs only when asked for.
     const bool split_ok = split_mode == 2 && idx.size() == 1 && p0.ros_sigma == 0.f && p0.rounding == 0 &&
+                          p0.ignition_mode != 3 && p0.ignition_period == 0 && (p0.burn_hours % 24) == 0 &&
                           p0.scenario_mode == 0 && !(p0.ros_threshold > 0.f) && p0.n_periods <= 4096;
 
     for (;;) {
@@ -826,6 +837,10 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             j.ign_cell = p.ignition_cell;
             j.scen_mode = p.scenario_mode;
             j.scen_fixed = p.scenario;
+            j.ign_period = p.ignition_period;
+            j.ign_cdf = p.ignition_mode == 3 ? L.ign_cdf : nullptr;
+            j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
+            j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
             j.sigma = p.ros_sigma;
             j.threshold = p.ros_threshold;
             j.seed = p.seed;
@@ -1495,6 +1510,47 @@ c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id) {
     dev_free(ctx, L.cells, n * sizeof(CellRec));
     dev_free(ctx, L.burnable, n * 4);
     dev_free(ctx, L.land, sizeof(LandDev));
+    dev_free(ctx, L.ign_cdf, n * 8);
+    return C2F_OK;
+}
+
+c2f_status c2f_set_ignition_map(c2f_ctx* ctx, int32_t landscape_id, const uint32_t* weights) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::lock_guard<std::mutex> lk2(ctx->objmu);
+    auto it = ctx->lands.find(landscape_id);
+    if (it == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", landscape_id);
+    Landscape& L = it->second;
+    if (L.inflight > 0)
+        return fail(ctx, C2F_EBUSY, "landscape %d is used by %d submitted requests", landscape_id, L.inflight);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t n = (size_t)L.ncells();
+    if (L.ign_cdf) {
+        (void)hipStreamSynchronize(ctx->main.stream);
+        drop_graph(ctx->main);
+        dev_free(ctx, L.ign_cdf, n * 8);
+        L.ign_cdf = nullptr;
+        L.ign_total = 0;
+    }
+    if (!weights) return C2F_OK;
+    // running sums in 64 bits: at most 2^31 cells of weight below 2^32
+    std::vector<uint64_t> cdf(n);
+    uint64_t run = 0;
+    for (size_t i = 0; i < n; ++i) {
+        run += weights[i];
+        cdf[i] = run;
+    }
+    uint64_t* d = nullptr;
+    c2f_status st = dev_alloc(ctx, (void**)&d, n * 8);
+    if (st != C2F_OK) return st;
+    if (hipMemcpy(d, cdf.data(), n * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_free(ctx, d, n * 8);
+        return fail(ctx, C2F_EDEVICE, "ignition map upload failed");
+    }
+    L.ign_cdf = d;
+    L.ign_total = run;
     return C2F_OK;
 }
 

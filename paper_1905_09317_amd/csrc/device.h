@@ -409,8 +409,10 @@ struct RateCtx {
 // Weather scenario and ignition cell of replication `rep` of a job
 // (Section 3.1, uncertainty sources (1) and (3)): a fixed scenario or
 // (x S) >> 32 from Philox tag 4; a fixed cell, the burnable cell (x |B|) >> 32
-// of the row-major burnable list from tag 3, or the burnable cell nearest
-// the centre.  ign = -1 when the landscape has no burnable cell.
+// of the row-major burnable list from tag 3, the burnable cell nearest the
+// centre, or a draw from the ignition map: with running weight sums C and
+// total W, the first cell whose C exceeds floor(x W / 2^32).  ign = -1 when
+// there is nothing to ignite.
 __device__ __forceinline__ void rep_draws(const Job& job, uint32_t rep, int& scen, int& ign) {
     scen = job.scen_fixed;
     if (job.scen_mode == 1) {
@@ -426,9 +428,31 @@ __device__ __forceinline__ void rep_draws(const Job& job, uint32_t rep, int& sce
             const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
             ign = job.burnable[((uint64_t)x.x * (uint64_t)nbn) >> 32];
         }
-    } else {
+    } else if (job.ign_mode == 2) {
         ign = job.land->centre_cell;
+    } else if (job.ign_total > 0) {
+        const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
+        const uint64_t W = job.ign_total;
+        // floor(x W / 2^32) without overflow: W < 2^63
+        const uint64_t t = (uint64_t)x.x * (W >> 32) + (((uint64_t)x.x * (W & 0xFFFFFFFFull)) >> 32);
+        // first index with C[i] > t (C is non-decreasing, C[n-1] = W > t)
+        int64_t lo = 0, hi = (int64_t)job.rows * job.cols - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (job.ign_cdf[mid] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        ign = (int)lo;
     }
+}
+
+// Does period p lie inside the daily burning window (the first burn_hours
+// hours of every day from the start of the run; assumption A5)?  The
+// period length divides 60 minutes whenever a window is set, so a period
+// lies wholly inside or outside it.
+__device__ __forceinline__ bool burning_period(const Job& job, int p) {
+    if (job.burn_hours <= 0) return true;
+    return (int)(((int64_t)p * job.period_min) % 1440) < job.burn_hours * 60;
 }
 
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by

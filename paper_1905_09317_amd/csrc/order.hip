@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void order_keys_kernel(const Job* __restrict__
         else hi = mid - 1;
     }
     const Job& job = jobs[lo];
-    if (p >= job.n_periods) return;
+    if (p >= job.n_periods || p < job.ign_period || !burning_period(job, p)) return;
     const uint32_t rep = (uint32_t)(job.rep_offset + (item - job.item_base));
     int scen, ign;
     rep_draws(job, rep, scen, ign);

@@ -248,7 +248,8 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             slots.tags[slot] = tag;
             const int ign = s_ign;
             if (ign >= 0 && rec_fuel(cells[ign].info) != 0) {
-                const uint32_t v = tag << kMinuteBits;          // minute 0
+                // the ignition takes the last minute before its period
+                const uint32_t v = (tag << kMinuteBits) | (uint32_t)(job.ign_period * P);
                 plane[ign] = v;
                 s_Q[0] = make_uint2((uint32_t)ign, v);
                 s_res = s_commit = 1;
@@ -303,7 +304,10 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             q_commit(wbase, (int)__popcll(m));
         };
 
-        for (int p = 0; p < job.n_periods; ++p) {
+        for (int p = job.ign_period; p < job.n_periods; ++p) {
+            // outside the daily burning window nothing spreads or ignites:
+            // the continuations and pending cells wait, unchanged
+            if (!burning_period(job, p)) continue;
             const int32_t s = p * P + 1;   // first minute of period p
             const int32_t e = (p + 1) * P; // last minute of period p
 
@@ -364,7 +368,9 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                 }
                 bool keep = false;
                 if (act) {
-                    const int32_t m0 = conts ? s : (int32_t)(lab & kMinuteMask) + 1;
+                    // a cell lit before p (an ignition waiting out the hours
+                    // outside the burning window) advances from p's start
+                    const int32_t m0 = conts ? s : max((int32_t)(lab & kMinuteMask) + 1, s);
                     c_evals += advance<R>(X, rec, c, p, m0, e, nbv, tag, rem, cand);
                     keep = (rem[0] | rem[1] | rem[2] | rem[3] | rem[4] | rem[5] | rem[6] | rem[7]) != 0;
                 } else {

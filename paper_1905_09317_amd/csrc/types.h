@@ -67,9 +67,12 @@ struct Job {
     int32_t n_scen, n_wp, period_min, n_periods;
     int32_t T, reps, rep_offset, item_base;
     int32_t rounding, ign_mode, ign_cell, scen_mode;
-    int32_t scen_fixed, pad0;
+    int32_t scen_fixed, ign_period;
     float sigma, threshold;
     uint64_t seed;
+    const uint64_t* ign_cdf;   // ignition map: running weight sums per cell (mode 3)
+    uint64_t ign_total;
+    int32_t burn_hours, pad1;  // daily burning window (0 = always)
     uint8_t* scar;             // outputs (device); NULL = not wanted
     int32_t* arr_period;
     int32_t* arr_minute;
