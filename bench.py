@@ -246,13 +246,102 @@ def served_bench(args) -> None:
     sim.close()
 
 
+def treatment_plans(w, n_plans: int, seed: int = 77):
+    """Fuel-treatment plans of a landscape: plan 0 is the landscape itself;
+    plan k > 0 cuts a 3-cell fuel break along a column and harvests 5 % of
+    the cells at random (both set to non-fuel)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    rows, cols = w.rows, w.cols
+    plans = [(np.zeros(0, np.int32), np.zeros(0, np.uint8))]
+    for _ in range(1, n_plans):
+        c0 = int(rng.integers(8, cols - 11))
+        strip = (np.arange(rows)[:, None] * cols + np.arange(c0, c0 + 3)[None, :]).ravel().astype(np.int32)
+        cut = rng.choice(rows * cols, rows * cols // 20, replace=False).astype(np.int32)
+        cells = np.concatenate([strip, cut])
+        plans.append((cells, np.zeros(cells.size, np.uint8)))
+    return plans
+
+
+def treatment_bench(args) -> None:
+    """Fuel-treatment batch: the batched Monte-Carlo landscape and 7 derived
+    plans, 256 replications each, in one fused launch (burn probability per
+    plan), against the same plans one launch each."""
+    import torch
+
+    from paper_1905_09317_amd import Request, Simulator
+
+    n_plans, reps = 8, 256
+    w = make_workload("batched")
+    sim = Simulator(0)
+    sim.set_stream(torch.cuda.current_stream())
+    base = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    lids = [base] + [sim.derive_landscape(base, c, f) for c, f in treatment_plans(w, n_plans)[1:]]
+    print(f"[bench] {n_plans} treatment plans of {w.rows}x{w.cols}, {reps} reps each", file=sys.stderr,
+          flush=True)
+    reqs = [Request(landscape=lid, weather=wx, n_periods=w.n_periods, reps=reps, seed=w.seed, sigma=w.sigma,
+                    rounding=w.rounding, precision=w.precision, ignition_mode=w.ignition_mode,
+                    scenario_mode=w.scenario_mode, outputs=("burn_count", "burned_cells"), device_out=True)
+            for lid in lids]
+    for _ in range(args.warmup):
+        sim.simulate_batch(reqs)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs = sim.simulate_batch(reqs)
+        st = sim.stats()
+        kms.append(st["kernel_ms"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the same plans, one launch each
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = [sim.simulate(r) for r in reqs]
+    torch.cuda.synchronize()
+    ms_alone = (time.perf_counter() - t0) * 1e3
+    same = all(torch.equal(a["burn_count"], b["burn_count"]) for a, b in zip(alone, outs))
+    alg_bytes = B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"]
+    kernel_ms = sum(kms) / len(kms)
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    cell_updates = n_plans * reps * w.rows * w.cols * w.n_periods
+    p_burn = [float(o["burn_count"].double().mean().item()) / reps for o in outs]
+    line = {
+        "metric": "cell-updates/s (reps x cells x periods), fuel-treatment batch",
+        "value": cell_updates / (ms / 1e3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"treatments-{n_plans}plans-{w.rows}x{w.cols}-{reps}reps", "plans": n_plans,
+                   "reps_per_plan": reps, "n_periods": w.n_periods, "scenarios": int(w.weather.shape[0]),
+                   "ros_sigma": w.sigma, "block_threads": st["block_threads"],
+                   "grid_blocks": st["grid_blocks"], "rep_order": st["rep_order"]},
+        "one_launch_per_plan": {"ms": ms_alone, "speedup": ms_alone / ms, "identical": bool(same)},
+        "mean_burn_probability": p_burn,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "c2f::propagate_kernel",
+                     "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes},
+    }
+    print(json.dumps(line), flush=True)
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single",
-                    choices=["single", "single64", "batched", "large", "tiny", "served"])
+                    choices=["single", "single64", "batched", "large", "tiny", "served", "treatments"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=0,
@@ -288,6 +377,9 @@ def main():
 
     if args.workload == "served":
         served_bench(args)
+        return
+    if args.workload == "treatments":
+        treatment_bench(args)
         return
 
     w = make_workload(args.workload)

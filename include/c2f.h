@@ -87,6 +87,18 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
                               float curing_pct, int32_t* landscape_id);
 c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id);
 
+/* A treatment variant of a loaded landscape (Section 1: harvested or
+ * non-fuel cells as fuel-management plans): a new landscape with the base's
+ * grid, elevation (its slopes are taken from the base's cell records), cell
+ * width, percent conifer and curing, and fuel[cells[k]] = fuels[k] for the
+ * n_edits edits (fuel 0 = harvested / non-fuel; later edits of a cell win).
+ * Cell records, burnable list and centre cell are rebuilt on the device.
+ * The base's ignition map is not carried over.  Plans of one base share a
+ * launch through c2f_simulate_batch; each plan's burn_count / reps is its
+ * burn-probability map. */
+c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, const int32_t* cells,
+                                const uint8_t* fuels, int32_t* landscape_id);
+
 /* Spatial ignition probability of a landscape (Section 3.1, uncertainty
  * (1)): weights[rows*cols] (host, row-major, copied) give cell i the
  * probability weights[i] / sum(weights) under ignition_mode 3.  The draw is

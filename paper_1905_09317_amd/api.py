@@ -128,6 +128,18 @@ class Simulator:
         self._check(self._L.c2f_unload_landscape(self._ctx, int(landscape)))
         self._lands.pop(landscape, None)
 
+    def derive_landscape(self, base: int, cells, fuels) -> int:
+        """A treatment variant of `base`: fuel[cells[k]] = fuels[k] (0 =
+        harvested / non-fuel); same grid, slopes and constants."""
+        c = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1)
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(fuels, dtype=np.uint8), c.shape))
+        out = ctypes.c_int32()
+        self._check(self._L.c2f_derive_landscape(self._ctx, int(base), ctypes.c_int64(c.size),
+                                                 c.ctypes.data_as(ctypes.c_void_p),
+                                                 f.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+        self._lands[out.value] = self._lands[base]
+        return out.value
+
     def set_ignition_map(self, landscape: int, weights):
         """Ignition probability per cell (ignition_mode 3): integer weights of
         the landscape's shape; None removes the map."""

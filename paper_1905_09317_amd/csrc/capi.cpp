@@ -1464,7 +1464,7 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     hipError_t e = hipMemcpyAsync(L.fuel, fuel, (size_t)n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && elev_m) e = hipMemcpyAsync(d_elev, elev_m, (size_t)n * 2, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = launch_prepare_landscape(L.fuel, d_elev, rows, cols, cell_m, pc_pct, curing_pct, L.cells, L.burnable,
+        e = launch_prepare_landscape(L.fuel, d_elev, nullptr, rows, cols, cell_m, pc_pct, curing_pct, L.cells, L.burnable,
                                      d_tiles, L.land, s);
     LandDev hl;
     if (e == hipSuccess) e = hipMemcpyAsync(&hl, L.land, sizeof hl, hipMemcpyDeviceToHost, s);
@@ -1480,6 +1480,101 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     if (hl.grad_overflow) {
         cleanup();
         return fail(ctx, C2F_EINVAL, "elevation too steep: a Horn gradient numerator exceeds 32767");
+    }
+    std::lock_guard<std::mutex> lk2(ctx->objmu);
+    const int32_t id = ctx->next_id++;
+    ctx->lands[id] = L;
+    *landscape_id = id;
+    return C2F_OK;
+}
+
+c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, const int32_t* cells,
+                                const uint8_t* fuels, int32_t* landscape_id) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!landscape_id) return fail(ctx, C2F_EINVAL, "landscape_id must be non-NULL");
+    if (n_edits < 0 || (n_edits > 0 && (!cells || !fuels)))
+        return fail(ctx, C2F_EINVAL, "need n_edits >= 0 and non-NULL cells/fuels");
+    Landscape B;
+    {
+        std::lock_guard<std::mutex> lk2(ctx->objmu);
+        auto it = ctx->lands.find(base_id);
+        if (it == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", base_id);
+        B = it->second;
+    }
+    const int64_t n = B.ncells();
+    for (int64_t k = 0; k < n_edits; ++k) {
+        if (cells[k] < 0 || cells[k] >= n)
+            return fail(ctx, C2F_EINVAL, "edit %lld: cell %d outside the grid", (long long)k, cells[k]);
+        if (fuels[k] > 15) return fail(ctx, C2F_EINVAL, "edit %lld: fuel code %d > 15", (long long)k, fuels[k]);
+    }
+    // one edit per cell, the last one given (the device applies them in parallel)
+    std::vector<int64_t> order((size_t)n_edits);
+    for (int64_t k = 0; k < n_edits; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cells[a] < cells[b]; });
+    std::vector<int32_t> ucells;
+    std::vector<uint8_t> ucodes;
+    for (size_t i = 0; i < order.size(); ++i) {
+        if (i + 1 < order.size() && cells[order[i + 1]] == cells[order[i]]) continue;
+        ucells.push_back(cells[order[i]]);
+        ucodes.push_back(fuels[order[i]]);
+    }
+    n_edits = (int64_t)ucells.size();
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->main.stream;
+    Landscape L;
+    L.rows = B.rows;
+    L.cols = B.cols;
+    L.cell_m = B.cell_m;
+    L.pc = B.pc;
+    L.curing = B.curing;
+    int32_t* d_tiles = nullptr;
+    int32_t* d_cells = nullptr;
+    uint8_t* d_codes = nullptr;
+    const int64_t n_tiles = tile_scratch_entries(n);
+    const size_t ne = (size_t)std::max<int64_t>(n_edits, 1);
+    auto temps = [&]() {
+        dev_free(ctx, d_tiles, (size_t)n_tiles * 4);
+        dev_free(ctx, d_cells, ne * 4);
+        dev_free(ctx, d_codes, ne);
+        d_tiles = nullptr;
+        d_cells = nullptr;
+        d_codes = nullptr;
+    };
+    auto cleanup = [&]() {
+        temps();
+        dev_free(ctx, L.fuel, (size_t)n);
+        dev_free(ctx, L.cells, (size_t)n * sizeof(CellRec));
+        dev_free(ctx, L.burnable, (size_t)n * 4);
+        dev_free(ctx, L.land, sizeof(LandDev));
+    };
+    c2f_status st = C2F_OK;
+    if ((st = dev_alloc(ctx, (void**)&L.fuel, (size_t)n)) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&L.cells, (size_t)n * sizeof(CellRec))) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&L.burnable, (size_t)n * 4)) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&L.land, sizeof(LandDev))) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&d_tiles, (size_t)n_tiles * 4)) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&d_cells, ne * 4)) != C2F_OK ||
+        (st = dev_alloc(ctx, (void**)&d_codes, ne)) != C2F_OK) {
+        cleanup();
+        return st;
+    }
+    // the base's fuel with the edits applied; slopes from the base's records
+    hipError_t e = hipMemcpyAsync(L.fuel, B.fuel, (size_t)n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && n_edits > 0)
+        e = hipMemcpyAsync(d_cells, ucells.data(), (size_t)n_edits * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && n_edits > 0)
+        e = hipMemcpyAsync(d_codes, ucodes.data(), (size_t)n_edits, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fuel_edits(L.fuel, d_cells, d_codes, n_edits, s);
+    if (e == hipSuccess)
+        e = launch_prepare_landscape(L.fuel, nullptr, B.cells, L.rows, L.cols, L.cell_m, L.pc, L.curing, L.cells,
+                                     L.burnable, d_tiles, L.land, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    temps();
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(ctx, C2F_EDEVICE, "derived landscape preparation failed: %s", hipGetErrorString(e));
     }
     std::lock_guard<std::mutex> lk2(ctx->objmu);
     const int32_t id = ctx->next_id++;

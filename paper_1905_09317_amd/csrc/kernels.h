@@ -11,11 +11,16 @@ namespace c2f {
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 
 // Cell records, burnable list, nearest-centre cell and landscape constants.
-// tile_scratch holds tile_scratch_entries(rows*cols) int32.
-hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, int rows, int cols,
-                                    int cell_m, float pc, float curing, CellRec* recs,
+// tile_scratch holds tile_scratch_entries(rows*cols) int32.  Slopes come
+// from elev (NULL = flat) or, when grad_from is set, from the Horn
+// numerators of those records.
+hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, const CellRec* grad_from,
+                                    int rows, int cols, int cell_m, float pc, float curing, CellRec* recs,
                                     int32_t* burnable, int32_t* tile_scratch, LandDev* land,
                                     hipStream_t s);
+
+// fuel[cells[k]] = codes[k] for k < n.
+hipError_t launch_fuel_edits(uint8_t* fuel, const int32_t* cells, const uint8_t* codes, int64_t n, hipStream_t s);
 int64_t tile_scratch_entries(int64_t n_cells);
 
 // Per (scenario, period) weather terms in FP64 and FP32; wx is [n_rows][4].

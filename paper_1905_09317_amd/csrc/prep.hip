@@ -40,8 +40,11 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
 
 // Cell records.  Horn's 3x3 gradient numerators with replicated edges:
 // gx = east column - west column (weights 1,2,1), gn = north row - south row.
-__global__ void cellrec_kernel(const uint8_t* __restrict__ fuel, const int16_t* __restrict__ elev, int rows,
-                               int cols, double cell_m, CellRec* __restrict__ recs, int32_t* __restrict__ overflow) {
+// grad_from (may be NULL): take the Horn numerators from these records (a
+// landscape derived from another with the same elevation) instead of elev.
+__global__ void cellrec_kernel(const uint8_t* __restrict__ fuel, const int16_t* __restrict__ elev,
+                               const CellRec* __restrict__ grad_from, int rows, int cols, double cell_m,
+                               CellRec* __restrict__ recs, int32_t* __restrict__ overflow) {
     const size_t n = (size_t)rows * cols;
     const int DR[8] = {0, -1, -1, -1, 0, 1, 1, 1};
     const int DC[8] = {1, 1, 0, -1, -1, -1, 0, 1};
@@ -54,7 +57,11 @@ __global__ void cellrec_kernel(const uint8_t* __restrict__ fuel, const int16_t* 
             if (rr >= 0 && rr < rows && cc >= 0 && cc < cols && fuel[(size_t)rr * cols + cc] != 0) mask |= 1u << k;
         }
         int gx = 0, gn = 0;
-        if (elev) {
+        if (grad_from) {
+            const uint32_t g = grad_from[i].grad;
+            gx = (int)(int16_t)(g & 0xFFFFu);
+            gn = (int)(int16_t)(g >> 16);
+        } else if (elev) {
             const int rn = r > 0 ? r - 1 : 0, rs = r < rows - 1 ? r + 1 : rows - 1;
             const int cw = c > 0 ? c - 1 : 0, ce = c < cols - 1 ? c + 1 : cols - 1;
             auto z = [&](int rr, int cc) { return (int)elev[(size_t)rr * cols + cc]; };
@@ -195,8 +202,8 @@ __global__ void landconst_kernel(LandDev* land, float pc, float curing, int cell
     land->centre_cell = (key == ~0ull) ? -1 : (int32_t)(key & 0xFFFFFFFFull);
 }
 
-hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, int rows, int cols,
-                                    int cell_m, float pc, float curing, CellRec* recs,
+hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, const CellRec* grad_from,
+                                    int rows, int cols, int cell_m, float pc, float curing, CellRec* recs,
                                     int32_t* burnable, int32_t* tile_scratch, LandDev* land,
                                     hipStream_t s) {
     const int64_t n = (int64_t)rows * cols;
@@ -205,8 +212,8 @@ hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, in
     // LandDev: zero, then centre key = max
     if ((e = launch_fill_u32((uint32_t*)land, sizeof(LandDev) / 4, 0u, s)) != hipSuccess) return e;
     if ((e = launch_fill_u32((uint32_t*)&land->centre_key, 2, 0xFFFFFFFFu, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(cellrec_kernel, dim3(g), dim3(256), 0, s, fuel, elev, rows, cols, (double)cell_m, recs,
-                       &land->grad_overflow);
+    hipLaunchKernelGGL(cellrec_kernel, dim3(g), dim3(256), 0, s, fuel, elev, grad_from, rows, cols,
+                       (double)cell_m, recs, &land->grad_overflow);
     const int n_tiles = (int)((n + kTile - 1) / kTile);
     hipLaunchKernelGGL(burnable_count_kernel, dim3(n_tiles), dim3(kTileThreads), 0, s, fuel, n, tile_scratch);
     hipLaunchKernelGGL(burnable_scan_kernel, dim3(1), dim3(1024), 0, s, tile_scratch, n_tiles, land);
@@ -217,6 +224,20 @@ hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, in
 }
 
 int64_t tile_scratch_entries(int64_t n_cells) { return (n_cells + kTile - 1) / kTile; }
+
+// fuel[cells[k]] = codes[k]: the edits of a derived landscape (cells are
+// checked on the host).
+__global__ void fuel_edit_kernel(uint8_t* __restrict__ fuel, const int32_t* __restrict__ cells,
+                                 const uint8_t* __restrict__ codes, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) fuel[cells[k]] = codes[k];
+}
+
+hipError_t launch_fuel_edits(uint8_t* fuel, const int32_t* cells, const uint8_t* codes, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fuel_edit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fuel, cells, codes, n);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------- weather table
 

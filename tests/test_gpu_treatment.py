@@ -1,0 +1,133 @@
+"""Fuel-treatment plans (harvested / non-fuel edits of one landscape,
+Section 1): a landscape derived on the device equals the same grid loaded
+from the host and the oracle on it, and plans sharing one launch equal
+each plan run alone, bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1905_09317_amd import C2FError, Request, Simulator, inputs
+
+from _helpers import assert_same_outputs, oracle_run
+
+pytestmark = pytest.mark.gpu
+OUTS = ("scar", "arrival_period", "arrival_minute", "burn_count", "burned_cells", "ignition_cell", "scenario")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim():
+    s = Simulator(0)
+    yield s
+    s.close()
+
+
+def _base(side=80, seed=160):
+    fuel = inputs.fuel_grid(side, side, seed)
+    elev = inputs.elevation_grid(side, side, seed + 1, elev_max=800.0)
+    wx = inputs.weather_scenarios(3, 10, seed + 2)
+    return fuel, elev, wx
+
+
+def _plan(fuel, seed, frac=0.06):
+    """A plan: a fuel break (a 3-cell column strip) and scattered harvested
+    cells set to non-fuel, plus a few cells re-typed to grass."""
+    rng = np.random.default_rng(seed)
+    rows, cols = fuel.shape
+    c0 = int(rng.integers(5, cols - 8))
+    strip = np.array([r * cols + c for r in range(rows) for c in range(c0, c0 + 3)], np.int32)
+    scatter = rng.choice(fuel.size, int(frac * fuel.size), replace=False).astype(np.int32)
+    grass = rng.choice(fuel.size, 40, replace=False).astype(np.int32)
+    cells = np.concatenate([strip, scatter, grass])
+    codes = np.concatenate([np.zeros(strip.size + scatter.size, np.uint8), np.full(grass.size, 12, np.uint8)])
+    edited = fuel.copy().ravel()
+    edited[cells] = codes          # numpy applies repeated indices in order: the last wins
+    return cells, codes, edited.reshape(fuel.shape)
+
+
+def test_derived_landscape_equals_fresh_load_and_oracle(sim):
+    _say("derived landscape")
+    fuel, elev, wx = _base()
+    cells, codes, edited = _plan(fuel, 1)
+    base = sim.load_landscape(fuel, elev)
+    der = sim.derive_landscape(base, cells, codes)
+    fresh = sim.load_landscape(edited, elev)
+    x = sim.set_weather(wx)
+    for p in (0, 4):
+        a = sim.eval_ros(der, x, scenario=1, period=p, rep=2, seed=3, sigma=0.2, rounding=1)
+        b = sim.eval_ros(fresh, x, scenario=1, period=p, rep=2, seed=3, sigma=0.2, rounding=1)
+        for k in ("hros", "bros", "fros", "lb", "raz", "x8", "q8"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    kw = dict(n_periods=10, reps=24, seed=9, sigma=0.15, rounding=1, ignition_mode=1, scenario_mode=1)
+    gd = sim.simulate(Request(landscape=der, weather=x, **kw))
+    gf = sim.simulate(Request(landscape=fresh, weather=x, **kw))
+    assert_same_outputs(gd, {k: np.asarray(v) for k, v in gf.items()}, OUTS, where="derived vs fresh")
+    ref = oracle_run(edited, elev, wx, **kw)
+    assert_same_outputs(gd, ref, OUTS, where="derived vs oracle")
+    for lid in (base, der, fresh):
+        sim.unload_landscape(lid)
+    sim.unset_weather(x)
+
+
+def test_plans_in_one_launch_equal_each_alone(sim):
+    _say("treatment batch")
+    fuel, elev, wx = _base(96, 170)
+    base = sim.load_landscape(fuel, elev)
+    plans = [base] + [sim.derive_landscape(base, *_plan(fuel, 10 + k)[:2]) for k in range(4)]
+    x = sim.set_weather(wx)
+    kw = dict(n_periods=10, reps=30, seed=21, sigma=0.15, rounding=1, ignition_mode=1, scenario_mode=1)
+    reqs = [Request(landscape=lid, weather=x, **kw) for lid in plans]
+    together = sim.simulate_batch(reqs)
+    for k, (lid, g) in enumerate(zip(plans, together)):
+        alone = sim.simulate(Request(landscape=lid, weather=x, **kw))
+        assert_same_outputs(g, {n: np.asarray(v) for n, v in alone.items()}, OUTS, where=f"plan {k}")
+    # every harvested cell of a plan never burns
+    for k in range(1, 5):
+        cells, codes, _ = _plan(fuel, 10 + k - 1)   # plans[k] was derived from seed 10 + k - 1
+        nonfuel = np.unique(cells[codes == 0])
+        last = {c: f for c, f in zip(cells, codes)}
+        nonfuel = np.array([c for c in nonfuel if last[c] == 0])
+        assert (np.asarray(together[k]["burn_count"])[nonfuel] == 0).all()
+    for lid in plans:
+        sim.unload_landscape(lid)
+    sim.unset_weather(x)
+
+
+def test_repeated_edits_keep_the_last(sim):
+    fuel, elev, wx = _base(40, 180)
+    base = sim.load_landscape(fuel, elev)
+    c = int(np.flatnonzero(fuel.ravel() != 0)[50])
+    der = sim.derive_landscape(base, [c, c, c], [0, 5, 2])
+    edited = fuel.copy().ravel()
+    edited[c] = 2
+    fresh = sim.load_landscape(edited.reshape(fuel.shape), elev)
+    x = sim.set_weather(wx)
+    a = sim.eval_ros(der, x)
+    b = sim.eval_ros(fresh, x)
+    np.testing.assert_array_equal(a["q8"], b["q8"])
+    np.testing.assert_array_equal(a["hros"], b["hros"])
+    for lid in (base, der, fresh):
+        sim.unload_landscape(lid)
+    sim.unset_weather(x)
+
+
+def test_derive_checks_its_arguments(sim):
+    fuel, elev, _ = _base(32, 190)
+    base = sim.load_landscape(fuel, elev)
+    with pytest.raises(C2FError) as e:
+        sim.derive_landscape(base, [fuel.size], [0])
+    assert e.value.status == -1
+    with pytest.raises(C2FError) as e:
+        sim.derive_landscape(base, [0], [16])
+    assert e.value.status == -1
+    with pytest.raises(C2FError) as e:
+        sim.derive_landscape(base + 1000, [0], [0])
+    assert e.value.status == -5
+    same = sim.derive_landscape(base, [], [])
+    sim.unload_landscape(same)
+    sim.unload_landscape(base)
