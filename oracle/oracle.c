@@ -487,7 +487,7 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     int32_t* scenario_out, int64_t* stats) {
     return oracle_simulate_ext(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
                                period_min, weather, reps, rep_offset, n_periods, seed, sigma, threshold,
-                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, scenario_mode,
+                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, 0.0, scenario_mode,
                                scenario_fixed, n_override, override_key, override_q, scar, arrival_period,
                                arrival_minute, burn_count, burned_cells, ignition_out, scenario_out, stats);
 }
@@ -506,12 +506,13 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         int32_t reps, int32_t rep_offset, int32_t n_periods, uint64_t seed,
                         double sigma, double threshold, int32_t rounding,
                         int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
-                        int32_t ignition_period, int32_t burn_hours,
+                        int32_t ignition_period, int32_t burn_hours, double burnout_ros,
                         int32_t scenario_mode, int32_t scenario_fixed,
                         int32_t n_override, const int32_t* override_key, const int32_t* override_q,
                         uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
                         uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
                         int32_t* scenario_out, int64_t* stats) {
+    if (!(burnout_ros >= 0.0) || !isfinite(burnout_ros)) return -1;
     if (check_land(rows, cols, cell_m, fuel, pc_pct, curing_pct, n_scen, n_wperiods, weather)) return -1;
     if (reps <= 0 || rep_offset < 0 || n_periods <= 0 || n_periods > n_wperiods || period_min <= 0)
         return -1;
@@ -666,6 +667,17 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         ++st_fbp;
                     }
                     b->qperiod = p;
+                    /* burn-out (A5 i): when the rates toward every burnable
+                     * neighbour fall below delta the cell stops spreading */
+                    if (burnout_ros > 0.0) {
+                        int32_t qmax = 0;
+                        for (int k = 0; k < 8; ++k) {
+                            int j = neighbour(&L, b->cell, k);
+                            if (j >= 0 && fuel[j] != 0 && b->q[k] > qmax) qmax = b->q[k];
+                        }
+                        if ((double)qmax < burnout_ros)
+                            for (int k = 0; k < 8; ++k) b->prog[k] = L.d[k];
+                    }
                 }
                 for (int k = 0; k < 8; ++k) {
                     int j = neighbour(&L, b->cell, k);

@@ -86,14 +86,17 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
  * ignition_weights[rows*cols] (integer weights); the ignition takes minute
  * ignition_period * period_min (0 <= ignition_period < n_periods, nothing
  * burns before); burn_hours in 1..24 limits spread and ignition to the first
- * burn_hours hours of every day counted from the start (0 = no limit). */
+ * burn_hours hours of every day counted from the start (0 = no limit);
+ * burnout_ros > 0 (m/min) burns a cell out when, at an evaluation of its
+ * rates for a period, its integer axis rates toward every in-grid burnable
+ * neighbour are below it (assumption A5 (i)): it spreads no further. */
 int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
                         const int16_t* elev, double pc_pct, double curing_pct,
                         int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,
                         int32_t reps, int32_t rep_offset, int32_t n_periods, uint64_t seed,
                         double sigma, double threshold, int32_t rounding,
                         int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
-                        int32_t ignition_period, int32_t burn_hours,
+                        int32_t ignition_period, int32_t burn_hours, double burnout_ros,
                         int32_t scenario_mode, int32_t scenario_fixed,
                         int32_t n_override, const int32_t* override_key, const int32_t* override_q,
                         uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
