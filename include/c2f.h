@@ -151,7 +151,12 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *                  = no limit; 1..23 = fire spreads and cells ignite only
  *                  in the first burn_hours hours of every day counted from
  *                  the start of the run (progress pauses outside them).
- *                  Needs a period length that divides 60 minutes. */
+ *                  Needs a period length that divides 60 minutes.
+ *   burnout_ros    burn-out threshold delta (m/min; assumption A5 (i); 0 =
+ *                  off): when a burning cell's rates are evaluated for a
+ *                  period and its integer axis rates toward every in-grid
+ *                  burnable neighbour are below delta, it spreads no further,
+ *                  in that period or later. */
 typedef struct {
     int32_t landscape_id, weather_id, reps, n_periods;
     uint64_t seed;
@@ -161,6 +166,7 @@ typedef struct {
     int32_t scenario_mode, scenario;
     int32_t rep_offset;
     int32_t ignition_period, burn_hours;
+    float burnout_ros;
 } c2f_sim_params;
 
 /* Outputs of a simulation (Section 3.6 (i) burn grids and their counts).

@@ -44,6 +44,7 @@ class Request:
     rep_offset: int = 0
     ignition_period: int = 0
     burn_hours: int = 0
+    burnout: float = 0.0
     outputs: tuple = OUTPUT_NAMES
     device_out: bool = False
 
@@ -52,7 +53,7 @@ class Request:
                          int(self.seed) & (2**64 - 1), float(self.sigma), float(self.threshold),
                          self.rounding, self.precision, self.ignition_mode, self.ignition_cell,
                          self.scenario_mode, self.scenario, self.rep_offset, self.ignition_period,
-                         self.burn_hours)
+                         self.burn_hours, float(self.burnout))
 
 
 @dataclass

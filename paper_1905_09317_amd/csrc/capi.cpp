@@ -700,6 +700,8 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, Landscape** L, We
     if (p->ignition_period < 0 || p->ignition_period >= p->n_periods)
         return fail(ctx, C2F_EINVAL, "ignition_period %d not in 0..%d", p->ignition_period, p->n_periods - 1);
     if (p->burn_hours < 0 || p->burn_hours > 24) return fail(ctx, C2F_EINVAL, "burn_hours must be 0..24");
+    if (!(p->burnout_ros >= 0.f) || !std::isfinite(p->burnout_ros))
+        return fail(ctx, C2F_EINVAL, "burnout_ros must be finite and >= 0");
     if (p->burn_hours > 0 && p->burn_hours < 24 && (w.period_min > 60 || 60 % w.period_min != 0))
         return fail(ctx, C2F_EINVAL, "burn_hours needs a period length dividing 60 minutes (got %d)",
                     w.period_min);
@@ -795,6 +797,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     // evaluation), so it runs only when asked for.
     const bool split_ok = split_mode == 2 && idx.size() == 1 && p0.ros_sigma == 0.f && p0.rounding == 0 &&
                           p0.ignition_mode != 3 && p0.ignition_period == 0 && (p0.burn_hours % 24) == 0 &&
+                          !(p0.burnout_ros > 0.f) &&
                           p0.scenario_mode == 0 && !(p0.ros_threshold > 0.f) && p0.n_periods <= 4096;
 
     for (;;) {
@@ -841,6 +844,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             j.ign_cdf = p.ignition_mode == 3 ? L.ign_cdf : nullptr;
             j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
             j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
+            j.burnout = p.burnout_ros;
             j.sigma = p.ros_sigma;
             j.threshold = p.ros_threshold;
             j.seed = p.seed;

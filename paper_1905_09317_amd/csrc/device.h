@@ -404,6 +404,7 @@ struct RateCtx {
     R sigma;
     int rounding;
     uint32_t rep;
+    float burnout;   // burn-out threshold on the integer axis rates (0 = off)
 };
 
 // Weather scenario and ignition cell of replication `rep` of a job

@@ -123,6 +123,19 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
         int32_t q[8];
         axis_q<R>(X, rec, c, (uint32_t)p, q);
         evals = 1;
+        if (X.burnout > 0.f) {
+            // burn-out (A5 (i)): every rate toward a burnable neighbour is
+            // below delta, so the cell spreads no further
+            int32_t qmax = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if ((nb >> k) & 1u) qmax = max(qmax, q[k]);
+            if ((double)qmax < (double)X.burnout) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) rem[k] = 0;
+                return evals;
+            }
+        }
         // minutes left in p; metres left per axis are below 2^16 (at most
         // the diagonal of a 20 km cell), so when q < r and n < r every
         // product below fits in 32 bits
@@ -271,6 +284,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         X.sigma = (R)job.sigma;
         X.rounding = job.rounding;
         X.rep = rep;
+        X.burnout = job.burnout;
 
         uint32_t c_entries = 0, c_conts = 0, c_evals = 0, c_cand = 0, c_impr = 0, c_ign = 0, c_rounds = 0;
         int max_list = 0;

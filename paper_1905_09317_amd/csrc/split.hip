@@ -359,6 +359,7 @@ __global__ __launch_bounds__(BLOCK, 2) void split_period_kernel(const Job* __res
     X.sigma = (R)job.sigma;
     X.rounding = job.rounding;
     X.rep = rep;
+    X.burnout = 0.f;
     const int rr0 = reg->cr0, rr1 = reg->cr1, rc0 = reg->cc0, rc1 = reg->cc1;   // cached rectangle
     const int32_t s = p * P + 1;     // first minute of period p
     const int32_t e = (p + 1) * P;   // last minute of period p

@@ -72,7 +72,8 @@ struct Job {
     uint64_t seed;
     const uint64_t* ign_cdf;   // ignition map: running weight sums per cell (mode 3)
     uint64_t ign_total;
-    int32_t burn_hours, pad1;  // daily burning window (0 = always)
+    int32_t burn_hours;        // daily burning window (0 = always)
+    float burnout;             // burn-out rate threshold, m/min (0 = off)
     uint8_t* scar;             // outputs (device); NULL = not wanted
     int32_t* arr_period;
     int32_t* arr_minute;
