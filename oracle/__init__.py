@@ -54,8 +54,9 @@ def _load():
         L.oracle_simulate_ext.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
                                           i32, i32, i32, u64, f64, f64, i32, i32, i32, P, i32, i32,
                                           f64, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+        L.oracle_scar_metrics.argtypes = [i64, i32, i32, P, P, P, P, P]
         for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_eval_ros_cells",
-                   "oracle_simulate", "oracle_simulate_ext"):
+                   "oracle_simulate", "oracle_simulate_ext", "oracle_scar_metrics"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -196,3 +197,21 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
     if rc != 0:
         raise ValueError("oracle_simulate_ext: bad input")
     return res
+
+
+def scar_metrics(arrival_minute, reference, *, period_min=60) -> dict:
+    """MSE and SSIM per period and the final delta_norm of the scars given by
+    arrival minutes [cells] against reference 0-1 scars [periods, cells]."""
+    a = np.ascontiguousarray(arrival_minute, dtype=np.int32).reshape(-1)
+    r = np.ascontiguousarray(reference, dtype=np.uint8)
+    r = r.reshape(r.shape[0], -1)
+    if r.shape[1] != a.size:
+        raise ValueError("reference scars must have one value per cell")
+    T = r.shape[0]
+    out = {"mse": np.zeros(T), "ssim": np.zeros(T), "delta_norm": np.zeros(1)}
+    rc = _load().oracle_scar_metrics(a.size, T, int(period_min), _ptr(a), _ptr(r), _ptr(out["mse"]),
+                                     _ptr(out["ssim"]), _ptr(out["delta_norm"]))
+    if rc != 0:
+        raise ValueError("oracle_scar_metrics: bad input")
+    out["delta_norm"] = float(out["delta_norm"][0])
+    return out

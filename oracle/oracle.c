@@ -768,3 +768,44 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
     free(ov_q);
     return 0;
 }
+
+/* Scar comparison of Section 4 (comparison methodology): for t = 1..T the
+ * simulated scar Y^t (cells whose arrival minute is in [0, t P]) against the
+ * reference 0-1 scar X^t = reference[t-1][.], by mean squared error and the
+ * structural similarity of Wang et al. (2004), evaluated over the whole grid
+ * with C1 = (0.01 L)^2, C2 = (0.03 L)^2, L = 1, standard deviations and
+ * covariance normalised by N - 1, and the denominator (mu_x^2 + mu_y^2 + C1)
+ * (sigma_x^2 + sigma_y^2 + C2) (the printed formula repeats the means in the
+ * second factor); delta_norm is the Frobenius norm of X^T - Y^T. */
+int oracle_scar_metrics(int64_t n_cells, int32_t n_periods, int32_t period_min, const int32_t* arrival_minute,
+                        const uint8_t* reference, double* mse, double* ssim, double* delta_norm) {
+    if (n_cells < 2 || n_periods < 1 || period_min < 1 || !arrival_minute || !reference) return -1;
+    const double N = (double)n_cells;
+    const double C1 = 0.01 * 0.01, C2 = 0.03 * 0.03;
+    for (int32_t t = 1; t <= n_periods; ++t) {
+        const uint8_t* X = reference + (size_t)(t - 1) * (size_t)n_cells;
+        const int64_t end = (int64_t)t * period_min;
+        double sx = 0.0, sy = 0.0;
+        for (int64_t i = 0; i < n_cells; ++i) {
+            sx += (double)(X[i] != 0);
+            sy += (double)(arrival_minute[i] >= 0 && arrival_minute[i] <= end);
+        }
+        const double mx = sx / N, my = sy / N;
+        double vx = 0.0, vy = 0.0, cxy = 0.0, se = 0.0;
+        for (int64_t i = 0; i < n_cells; ++i) {
+            const double x = (double)(X[i] != 0);
+            const double y = (double)(arrival_minute[i] >= 0 && arrival_minute[i] <= end);
+            vx += (x - mx) * (x - mx);
+            vy += (y - my) * (y - my);
+            cxy += (x - mx) * (y - my);
+            se += (x - y) * (x - y);
+        }
+        vx /= (N - 1.0);
+        vy /= (N - 1.0);
+        cxy /= (N - 1.0);
+        if (mse) mse[t - 1] = se / N;
+        if (ssim) ssim[t - 1] = ((2.0 * mx * my + C1) * (2.0 * cxy + C2)) / ((mx * mx + my * my + C1) * (vx + vy + C2));
+        if (delta_norm && t == n_periods) *delta_norm = sqrt(se);
+    }
+    return 0;
+}

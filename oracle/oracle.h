@@ -103,6 +103,14 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
                         int32_t* scenario_out, int64_t* stats);
 
+/* Scar comparison (Section 4): per period t = 1..n_periods, the simulated
+ * scar {arrival_minute in [0, t period_min]} against reference[t-1][n_cells]
+ * (0-1): mse[t-1], ssim[t-1] (global SSIM, C1 = 1e-4, C2 = 9e-4, N - 1
+ * normalisation), and delta_norm = Frobenius norm of the difference at the
+ * last period.  Outputs may be NULL. */
+int oracle_scar_metrics(int64_t n_cells, int32_t n_periods, int32_t period_min, const int32_t* arrival_minute,
+                        const uint8_t* reference, double* mse, double* ssim, double* delta_norm);
+
 #ifdef __cplusplus
 }
 #endif
