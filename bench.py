@@ -47,10 +47,16 @@ TRAFFIC = {
 }
 
 
-def kernel_digest() -> str:
+# The same for the scar comparison kernel (one launch per comparison of the
+# 2048^2 x 48-period workload).
+SCAR_SOURCES = ("metrics.hip",)
+SCAR_TRAFFIC = ("80d01cc9a8a45579", 219_159_903)
+
+
+def kernel_digest(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1905_09317_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -335,13 +341,76 @@ def treatment_bench(args) -> None:
     sim.close()
 
 
+def scar_bench(args) -> None:
+    """Scar comparison (Section 4 metrics): the 2048^2 x 48 h single fire in
+    FP32 against its FP64 run, period by period (48 reference scars of
+    4.2M cells resident in HBM)."""
+    import torch
+
+    from paper_1905_09317_amd import Request, Simulator
+
+    w = make_workload("single")
+    sim = Simulator(0)
+    sim.set_stream(torch.cuda.current_stream())
+    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    kw = dict(n_periods=w.n_periods, ignition_mode=w.ignition_mode, outputs=("arrival_minute",),
+              device_out=True)
+    a64 = sim.simulate(Request(landscape=land, weather=wx, precision=0, **kw))["arrival_minute"][0]
+    a32 = sim.simulate(Request(landscape=land, weather=wx, precision=1, **kw))["arrival_minute"][0]
+    t = torch.arange(1, w.n_periods + 1, device=a64.device, dtype=torch.int32)[:, None] * w.period_min
+    ref = ((a64[None] >= 0) & (a64[None] <= t)).to(torch.uint8).contiguous()
+    res = torch.empty(2 * w.n_periods + 1, dtype=torch.float64, device=a64.device)
+    for _ in range(args.warmup):
+        sim.compare_scars_async(a32, ref, res, period_min=w.period_min)
+    # the comparisons queue back to back on torch's stream (results stay in
+    # HBM); HIP events on that stream time the device work
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        sim.compare_scars_async(a32, ref, res, period_min=w.period_min)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = ev0.elapsed_time(ev1) / args.steps
+    r = res.cpu().numpy()
+    m = {"mse": r[:w.n_periods], "ssim": r[w.n_periods:2 * w.n_periods], "delta_norm": float(r[-1])}
+    t0 = time.perf_counter()
+    sim.compare_scars(a32, ref, period_min=w.period_min)
+    sync_ms = (time.perf_counter() - t0) * 1e3
+    n = w.rows * w.cols
+    alg = w.n_periods * n + 4 * n            # every reference scar once, the arrival field once
+    line = {
+        "metric": "scar comparisons/s (cells x periods)",
+        "value": w.n_periods * n / (ms / 1e3),
+        "unit": "cell-periods/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "wall_ms_per_step": wall_ms, "sync_call_ms": sync_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"scars-{w.rows}x{w.cols}-{w.n_periods}periods", "periods": w.n_periods,
+                   "cells": n},
+        "final": {"mse": float(m["mse"][-1]), "ssim": float(m["ssim"][-1]), "delta_norm": m["delta_norm"]},
+        "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": SCAR_TRAFFIC[1] if kernel_digest(SCAR_SOURCES) == SCAR_TRAFFIC[0] else None,
+                     "kernel": "c2f::scar_counts_rows_kernel<16> (the whole comparison in one launch)",
+                     "kernel_ms": ms, "alg_bytes_per_launch": alg},
+    }
+    print(json.dumps(line), flush=True)
+    sim.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single",
-                    choices=["single", "single64", "batched", "large", "tiny", "served", "treatments"])
+                    choices=["single", "single64", "batched", "large", "tiny", "served", "treatments",
+                             "scars"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=0,
@@ -380,6 +449,9 @@ def main():
         return
     if args.workload == "treatments":
         treatment_bench(args)
+        return
+    if args.workload == "scars":
+        scar_bench(args)
         return
 
     w = make_workload(args.workload)

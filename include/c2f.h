@@ -99,6 +99,33 @@ c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id);
 c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, const int32_t* cells,
                                 const uint8_t* fuels, int32_t* landscape_id);
 
+/* Scar comparison (Section 4, comparison methodology).  For t = 1..n_periods
+ * the simulated scar Y^t = {cells with arrival_minute in [0, t period_min]}
+ * (one replication's arrival_minute output, -1 = unburned) is compared with
+ * the reference 0-1 scar X^t = reference[t-1][.] ([n_periods][n_cells],
+ * nonzero = burned): mse[t-1] = mean (X - Y)^2; ssim[t-1] = the structural
+ * similarity of Wang et al. (2004) over the whole grid, ((2 mu_x mu_y + C1)
+ * (2 sigma_xy + C2)) / ((mu_x^2 + mu_y^2 + C1)(sigma_x^2 + sigma_y^2 + C2)),
+ * C1 = 1e-4, C2 = 9e-4, (co)variances normalised by N - 1; *delta_norm =
+ * the Frobenius norm of X - Y at the last period.  Inputs are device
+ * pointers when on_device, else host (copied); outputs are host arrays
+ * (any may be NULL).  Synchronous on the context's stream.
+ * 2 <= n_cells < 2^31, 1 <= n_periods <= 65535. */
+c2f_status c2f_compare_scars(c2f_ctx* ctx, int64_t n_cells, int32_t n_periods, int32_t period_min,
+                             const int32_t* arrival_minute, const uint8_t* reference, int32_t on_device,
+                             double* mse, double* ssim, double* delta_norm);
+
+/* The same comparison ordered on the context's stream without waiting, for
+ * callers that keep the results in device memory: arrival_minute,
+ * reference and results are device pointers; results receives [2 n_periods
+ * + 1] doubles (mse, then ssim, then delta_norm) once the stream reaches
+ * the work.  The context keeps its count buffer between calls, so calls on
+ * one stream follow each other safely; calls of one context on different
+ * streams (c2f_set_stream between them) must not overlap.  The argument
+ * checks of c2f_compare_scars apply. */
+c2f_status c2f_compare_scars_async(c2f_ctx* ctx, int64_t n_cells, int32_t n_periods, int32_t period_min,
+                                   const int32_t* arrival_minute, const uint8_t* reference, double* results);
+
 /* Spatial ignition probability of a landscape (Section 3.1, uncertainty
  * (1)): weights[rows*cols] (host, row-major, copied) give cell i the
  * probability weights[i] / sum(weights) under ignition_mode 3.  The draw is

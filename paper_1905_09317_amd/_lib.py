@@ -100,6 +100,8 @@ def load() -> ctypes.CDLL:
         "c2f_set_rep_order": ([P, i32], i32),
         "c2f_set_ignition_map": ([P, i32, P], i32),
         "c2f_derive_landscape": ([P, i32, ctypes.c_int64, P, P, P], i32),
+        "c2f_compare_scars": ([P, ctypes.c_int64, i32, i32, P, P, i32, P, P, P], i32),
+        "c2f_compare_scars_async": ([P, ctypes.c_int64, i32, i32, P, P, P], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -114,4 +116,5 @@ DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2
             "c2f_simulate_batch", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
             "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
             "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_period_split", "c2f_set_rep_order",
-            "c2f_set_ignition_map", "c2f_derive_landscape")
+            "c2f_set_ignition_map", "c2f_derive_landscape", "c2f_compare_scars",
+            "c2f_compare_scars_async")

@@ -129,6 +129,56 @@ class Simulator:
         self._check(self._L.c2f_unload_landscape(self._ctx, int(landscape)))
         self._lands.pop(landscape, None)
 
+    def compare_scars(self, arrival_minute, reference, period_min: int = 60) -> dict:
+        """MSE and SSIM per period and the last period's Frobenius norm of the
+        scars given by one replication's arrival minutes against reference
+        0-1 scars [periods, cells].  torch tensors on the device stay there."""
+        on_dev = hasattr(arrival_minute, "is_cuda") and arrival_minute.is_cuda
+        if on_dev:
+            import torch
+            a = arrival_minute.contiguous().view(-1).to(torch.int32)
+            r = reference.contiguous().to(torch.uint8)
+            r = r.view(r.shape[0], -1)
+            self.set_stream(torch.cuda.current_stream(self._device))
+            pa, pr, n, T = a.data_ptr(), r.data_ptr(), a.numel(), r.shape[0]
+            if r.shape[1] != n:
+                raise ValueError("reference scars must have one value per cell")
+        else:
+            a = np.ascontiguousarray(arrival_minute, dtype=np.int32).reshape(-1)
+            r = np.ascontiguousarray(reference, dtype=np.uint8)
+            r = r.reshape(r.shape[0], -1)
+            if r.shape[1] != a.size:
+                raise ValueError("reference scars must have one value per cell")
+            pa, pr, n, T = a.ctypes.data, r.ctypes.data, a.size, r.shape[0]
+        out = {"mse": np.zeros(T), "ssim": np.zeros(T)}
+        dn = ctypes.c_double()
+        self._check(self._L.c2f_compare_scars(
+            self._ctx, ctypes.c_int64(n), int(T), int(period_min), ctypes.c_void_p(pa), ctypes.c_void_p(pr),
+            1 if on_dev else 0, out["mse"].ctypes.data_as(ctypes.c_void_p),
+            out["ssim"].ctypes.data_as(ctypes.c_void_p), ctypes.byref(dn)))
+        out["delta_norm"] = dn.value
+        return out
+
+    def compare_scars_async(self, arrival_minute, reference, results, period_min: int = 60):
+        """compare_scars on device tensors, ordered on torch's current stream
+        without waiting: results (float64, 2 T + 1 elements on the device)
+        receives mse[T], then ssim[T], then the Frobenius norm."""
+        import torch
+        a = arrival_minute.contiguous().view(-1).to(torch.int32)
+        r = reference.contiguous().to(torch.uint8)
+        r = r.view(r.shape[0], -1)
+        n, T = a.numel(), r.shape[0]
+        if r.shape[1] != n:
+            raise ValueError("reference scars must have one value per cell")
+        if (not results.is_cuda or results.dtype != torch.float64 or not results.is_contiguous()
+                or results.numel() < 2 * T + 1):
+            raise ValueError("results must be a contiguous float64 device tensor of 2 T + 1 elements")
+        self.set_stream(torch.cuda.current_stream(self._device))
+        self._check(self._L.c2f_compare_scars_async(
+            self._ctx, ctypes.c_int64(n), int(T), int(period_min), ctypes.c_void_p(a.data_ptr()),
+            ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(results.data_ptr())))
+        return results
+
     def derive_landscape(self, base: int, cells, fuels) -> int:
         """A treatment variant of `base`: fuel[cells[k]] = fuels[k] (0 =
         harvested / non-fuel); same grid, slopes and constants."""

@@ -177,8 +177,11 @@ struct c2f_ctx {
     std::mutex errmu;
     std::string err;
 
-    std::mutex mu;   // serialises the synchronous entry points; guards `main`
+    std::mutex mu;   // serialises the synchronous entry points; guards `main` and `metric_buf`
     Exec main;
+    void* metric_buf = nullptr;   // scar comparison counts and results, kept between calls
+    size_t metric_bytes = 0;
+    size_t metric_periods = 0;    // periods metric_buf is laid out for
 
     // Landscapes and weather.  Inserting or erasing needs `mu` and `objmu`;
     // lookups hold either; the in-flight counts need `objmu`.
@@ -1397,6 +1400,7 @@ void c2f_destroy(c2f_ctx* ctx) {
     for (auto& ln : ctx->lanes) exec_release(ctx, ln->ex);
     ctx->lanes.clear();
     exec_release(ctx, ctx->main);
+    if (ctx->metric_buf) (void)hipFree(ctx->metric_buf);
     for (auto& kv : ctx->lands) {
         (void)hipFree(kv.second.fuel);
         (void)hipFree(kv.second.cells);
@@ -1610,6 +1614,127 @@ c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id) {
     dev_free(ctx, L.burnable, n * 4);
     dev_free(ctx, L.land, sizeof(LandDev));
     dev_free(ctx, L.ign_cdf, n * 8);
+    return C2F_OK;
+}
+
+namespace {
+// Shared checks of the scar comparison entry points.
+c2f_status check_scar_args(c2f_ctx* ctx, int64_t n_cells, int32_t n_periods, int32_t period_min,
+                           const void* arrival_minute, const void* reference) {
+    if (n_cells < 2 || n_cells > 0x7FFFFFFEll) return fail(ctx, C2F_EINVAL, "n_cells must be in 2..2^31-2");
+    if (n_periods < 1 || n_periods > 65535) return fail(ctx, C2F_EINVAL, "n_periods must be in 1..65535");
+    if (period_min < 1) return fail(ctx, C2F_EINVAL, "period_min must be >= 1");
+    if (!arrival_minute || !reference) return fail(ctx, C2F_EINVAL, "arrival_minute and reference must be non-NULL");
+    return C2F_OK;
+}
+
+// The context's scar comparison buffer, laid out for its capacity C >= T
+// periods: counts (3 C u64) and the ticket of the last finishing block, both
+// zero between launches (a launch clears what it used), then 2 C + 1 f64
+// results.  The layout depends on C only, so results never land where a
+// later launch's counts must be zero.  Grown on demand (work queued on s
+// before a regrowth is waited for; a new buffer is zeroed on s).  Needs
+// ctx->mu.
+c2f_status scar_buffers(c2f_ctx* ctx, size_t T, hipStream_t s, unsigned long long** cnt, uint32_t** ticket,
+                        double** out) {
+    if (ctx->metric_periods < T) {
+        const size_t C = T;
+        const size_t need = ((C * 24 + 255) & ~(size_t)255) + 256 + (2 * C + 1) * 8;
+        if (ctx->metric_buf) {
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+            dev_free(ctx, ctx->metric_buf, ctx->metric_bytes);
+            ctx->metric_buf = nullptr;
+            ctx->metric_bytes = 0;
+            ctx->metric_periods = 0;
+        }
+        const c2f_status st = dev_alloc(ctx, &ctx->metric_buf, need);
+        if (st != C2F_OK) return st;
+        ctx->metric_bytes = need;
+        const size_t zero_bytes = ((C * 24 + 255) & ~(size_t)255) + 256;
+        const hipError_t e = launch_fill_u32((uint32_t*)ctx->metric_buf, zero_bytes / 4, 0u, s);
+        if (e != hipSuccess) {
+            dev_free(ctx, ctx->metric_buf, ctx->metric_bytes);
+            ctx->metric_buf = nullptr;
+            ctx->metric_bytes = 0;
+            return fail(ctx, C2F_EDEVICE, "clearing the scar count buffer failed: %s", hipGetErrorString(e));
+        }
+        ctx->metric_periods = C;
+    }
+    const size_t cnt_bytes = (ctx->metric_periods * 24 + 255) & ~(size_t)255;
+    *cnt = (unsigned long long*)ctx->metric_buf;
+    *ticket = (uint32_t*)((char*)ctx->metric_buf + cnt_bytes);
+    *out = (double*)((char*)ctx->metric_buf + cnt_bytes + 256);
+    return C2F_OK;
+}
+}  // namespace
+
+c2f_status c2f_compare_scars(c2f_ctx* ctx, int64_t n_cells, int32_t n_periods, int32_t period_min,
+                             const int32_t* arrival_minute, const uint8_t* reference, int32_t on_device,
+                             double* mse, double* ssim, double* delta_norm) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    c2f_status st = check_scar_args(ctx, n_cells, n_periods, period_min, arrival_minute, reference);
+    if (st != C2F_OK) return st;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->main.stream;
+    const size_t n = (size_t)n_cells, T = (size_t)n_periods;
+    unsigned long long* d_cnt = nullptr;
+    uint32_t* d_ticket = nullptr;
+    double* d_out = nullptr;
+    if ((st = scar_buffers(ctx, T, s, &d_cnt, &d_ticket, &d_out)) != C2F_OK) return st;
+    int32_t* d_arr = nullptr;
+    uint8_t* d_ref = nullptr;
+    auto cleanup = [&]() {
+        if (!on_device) {
+            dev_free(ctx, d_arr, n * 4);
+            dev_free(ctx, d_ref, n * T);
+        }
+    };
+    if (on_device) {
+        d_arr = const_cast<int32_t*>(arrival_minute);
+        d_ref = const_cast<uint8_t*>(reference);
+    } else if ((st = dev_alloc(ctx, (void**)&d_arr, n * 4)) != C2F_OK ||
+               (st = dev_alloc(ctx, (void**)&d_ref, n * T)) != C2F_OK) {
+        cleanup();
+        return st;
+    }
+    hipError_t e = hipSuccess;
+    if (!on_device) {
+        e = hipMemcpyAsync(d_arr, arrival_minute, n * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_ref, reference, n * T, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess)
+        e = launch_scar_metrics(d_arr, d_ref, n_cells, n_periods, period_min, d_cnt, d_ticket, d_out, s);
+    std::vector<double> out(2 * T + 1);
+    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), d_out, out.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(ctx, C2F_EDEVICE, "scar comparison failed: %s", hipGetErrorString(e));
+    if (mse) std::copy(out.begin(), out.begin() + (ptrdiff_t)T, mse);
+    if (ssim) std::copy(out.begin() + (ptrdiff_t)T, out.begin() + (ptrdiff_t)(2 * T), ssim);
+    if (delta_norm) *delta_norm = out[2 * T];
+    return C2F_OK;
+}
+
+c2f_status c2f_compare_scars_async(c2f_ctx* ctx, int64_t n_cells, int32_t n_periods, int32_t period_min,
+                                   const int32_t* arrival_minute, const uint8_t* reference, double* results) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    c2f_status st = check_scar_args(ctx, n_cells, n_periods, period_min, arrival_minute, reference);
+    if (st != C2F_OK) return st;
+    if (!results) return fail(ctx, C2F_EINVAL, "results must be non-NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->main.stream;
+    const size_t T = (size_t)n_periods;
+    unsigned long long* d_cnt = nullptr;
+    uint32_t* d_ticket = nullptr;
+    double* d_out = nullptr;
+    if ((st = scar_buffers(ctx, T, s, &d_cnt, &d_ticket, &d_out)) != C2F_OK) return st;
+    hipError_t e =
+        launch_scar_metrics(arrival_minute, reference, n_cells, n_periods, period_min, d_cnt, d_ticket, results, s);
+    if (e != hipSuccess) return fail(ctx, C2F_EDEVICE, "scar comparison failed: %s", hipGetErrorString(e));
     return C2F_OK;
 }
 

@@ -19,6 +19,14 @@ hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, co
                                     int32_t* burnable, int32_t* tile_scratch, LandDev* land,
                                     hipStream_t s);
 
+// Scar comparison in one launch: out[t] = MSE, out[T + t] = SSIM of period
+// t, out[2T] = Frobenius norm of the last period's difference.  counts (3 T
+// u64) and *ticket must be zero on entry and are zero again once the launch
+// ends; launches sharing them must be ordered (one stream).
+// 2 <= n, 1 <= T <= 65535.
+hipError_t launch_scar_metrics(const int32_t* arrival, const uint8_t* reference, int64_t n, int T, int period_min,
+                               unsigned long long* counts, uint32_t* ticket, double* out, hipStream_t s);
+
 // fuel[cells[k]] = codes[k] for k < n.
 hipError_t launch_fuel_edits(uint8_t* fuel, const int32_t* cells, const uint8_t* codes, int64_t n, hipStream_t s);
 int64_t tile_scratch_entries(int64_t n_cells);
