@@ -53,7 +53,7 @@ def _load():
                                       i32, P, P, P, P, P, P, P, P, P, P]
         L.oracle_simulate_ext.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
                                           i32, i32, i32, u64, f64, f64, i32, i32, i32, P, i32, i32,
-                                          f64, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+                                          f64, i32, P, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.oracle_scar_metrics.argtypes = [i64, i32, i32, P, P, P, P, P]
         for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_eval_ros_cells",
                    "oracle_simulate", "oracle_simulate_ext", "oracle_scar_metrics"):
@@ -150,14 +150,16 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
              sigma=0.0, threshold=0.0, rounding=0, ignition_mode=0, ignition_cell=0,
              scenario_mode=0, scenario=0, period_min=60, pc=50.0, curing=80.0,
              overrides=None, want_rep_outputs=True, ignition_weights=None, ignition_period=0,
-             burn_hours=0, burnout=0.0) -> dict:
+             burn_hours=0, burnout=0.0, ignitions=None) -> dict:
     """Run the minute-stepping reference simulation.
 
     overrides: optional (keys int32 [n,3] of (rep, period, cell), q int32 [n,8]).
     ignition_mode 3 draws the ignition from ignition_weights (uint32 per
     cell); ignition_period starts the fire at that period; burn_hours (1..24)
     is the daily burning window (0 = always); burnout (m/min, 0 = off) is the
-    rate below which a burning cell burns out.
+    rate below which a burning cell burns out.  ignitions: (cell, period)
+    pairs [k, 2] lit as the clock reaches their periods (ignition_mode 4,
+    set by passing them).
     Returns scar/arrival_period/arrival_minute [reps, rows*cols] (if wanted),
     burn_count [rows*cols], burned_cells/ignition_cell/scenario [reps], stats [3].
     """
@@ -184,12 +186,16 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
         iw = np.ascontiguousarray(ignition_weights, dtype=np.uint32).reshape(-1)
         if iw.size != n:
             raise ValueError("ignition_weights must hold one weight per cell")
+    seeds = None
+    if ignitions is not None:
+        seeds = np.ascontiguousarray(ignitions, dtype=np.int32).reshape(-1, 2)
+        ignition_mode = 4
     rc = _load().oracle_simulate_ext(
         rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc), float(curing), w.shape[0],
         w.shape[1], int(period_min), _ptr(w), int(reps), int(rep_offset), int(n_periods),
         int(seed) & (2**64 - 1), float(sigma), float(threshold), int(rounding),
         int(ignition_mode), int(ignition_cell), _ptr(iw), int(ignition_period), int(burn_hours),
-        float(burnout),
+        float(burnout), 0 if seeds is None else seeds.shape[0], _ptr(seeds),
         int(scenario_mode), int(scenario), n_ov,
         _ptr(ok), _ptr(oq), _ptr(res.get("scar")), _ptr(res.get("arrival_period")),
         _ptr(res.get("arrival_minute")), _ptr(res["burn_count"]), _ptr(res["burned_cells"]),

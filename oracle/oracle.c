@@ -487,7 +487,7 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     int32_t* scenario_out, int64_t* stats) {
     return oracle_simulate_ext(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
                                period_min, weather, reps, rep_offset, n_periods, seed, sigma, threshold,
-                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, 0.0, scenario_mode,
+                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, 0.0, 0, NULL, scenario_mode,
                                scenario_fixed, n_override, override_key, override_q, scar, arrival_period,
                                arrival_minute, burn_count, burned_cells, ignition_out, scenario_out, stats);
 }
@@ -507,6 +507,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         double sigma, double threshold, int32_t rounding,
                         int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
                         int32_t ignition_period, int32_t burn_hours, double burnout_ros,
+                        int32_t n_ignitions, const int32_t* ignition_list,
                         int32_t scenario_mode, int32_t scenario_fixed,
                         int32_t n_override, const int32_t* override_key, const int32_t* override_q,
                         uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
@@ -519,10 +520,17 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
     if ((int64_t)n_periods * period_min > 0x7FFFFFF0ll) return -1;
     if (!(sigma >= 0.0) || !isfinite(threshold) || (rounding != 0 && rounding != 1)) return -1;
     const int64_t n = (int64_t)rows * cols;
-    if (ignition_mode < 0 || ignition_mode > 3) return -1;
+    if (ignition_mode < 0 || ignition_mode > 4) return -1;
     if (ignition_mode == 0 && (ignition_cell < 0 || ignition_cell >= n)) return -1;
     if (ignition_mode == 3 && !ignition_weights) return -1;
     if (ignition_period < 0 || ignition_period >= n_periods) return -1;
+    if (ignition_mode == 4) {
+        if (n_ignitions < 1 || !ignition_list) return -1;
+        for (int32_t k = 0; k < n_ignitions; ++k) {
+            const int32_t c = ignition_list[2 * k], p = ignition_list[2 * k + 1];
+            if (c < 0 || c >= n || p < 0 || p >= n_periods) return -1;
+        }
+    }
     if (burn_hours < 0 || burn_hours > 24) return -1;
     if (scenario_mode < 0 || scenario_mode > 1) return -1;
     if (scenario_mode == 0 && (scenario_fixed < 0 || scenario_fixed >= n_scen)) return -1;
@@ -582,6 +590,23 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
         }
     }
 
+    /* ignition-point list (Section 3.2 (iii): cells paired with their
+     * ignition periods), ordered by period; entries of one period keep the
+     * given order (insertion sort, stable) */
+    int32_t n_seed = ignition_mode == 4 ? n_ignitions : 0;
+    int32_t* seeds = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(n_seed > 0 ? n_seed : 1));
+    for (int32_t i = 0; i < n_seed; ++i) {
+        int32_t c = ignition_list[2 * i], p = ignition_list[2 * i + 1];
+        int32_t j = i - 1;
+        while (j >= 0 && seeds[2 * j + 1] > p) {
+            seeds[2 * (j + 1)] = seeds[2 * j];
+            seeds[2 * (j + 1) + 1] = seeds[2 * j + 1];
+            --j;
+        }
+        seeds[2 * (j + 1)] = c;
+        seeds[2 * (j + 1) + 1] = p;
+    }
+
     /* total ignition weight (spatial ignition map) */
     uint64_t ign_total = 0;
     if (ignition_mode == 3)
@@ -614,6 +639,8 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
             }
         } else if (ignition_mode == 2) {
             ign = centre_cell;
+        } else if (ignition_mode == 4) {
+            ign = seeds[0];
         } else {
             /* spatial ignition probability (Section 3.1, uncertainty (1)):
              * cell i with probability w_i / W.  The draw x (32 bits, tag 3)
@@ -636,9 +663,11 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
         for (int64_t i = 0; i < n; ++i) arrival[i] = INF_T;
         memset(reached, 0, (size_t)n);
         size_t nb = 0, np = 0;
-        /* the ignition takes the last minute before its period */
-        const int32_t m0 = ignition_period * P;
-        if (ign >= 0 && fuel[ign] != 0) {
+        /* the ignition takes the last minute before its period; a list's
+         * fires are lit as the clock reaches their periods (below) */
+        const int32_t m0 = (ignition_mode == 4 ? seeds[1] : ignition_period) * P;
+        int32_t si = 0;   /* next list entry to light */
+        if (ignition_mode != 4 && ign >= 0 && fuel[ign] != 0) {
             arrival[ign] = m0;
             burn[0].cell = ign;
             burn[0].qperiod = -1;
@@ -648,7 +677,27 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
         }
         /* Step 2: fire dynamics, one clock minute at a time; outside the
          * daily burning window nothing spreads or ignites */
-        for (int32_t m = m0 + 1; m <= T && (nb > 0 || np > 0); ++m) {
+        for (int32_t m = m0 + 1; m <= T && (nb > 0 || np > 0 || si < n_seed); ++m) {
+            /* list ignitions of period p take minute p P: lit before minute
+             * p P + 1 is stepped, inside or outside the burning window, on a
+             * cell with fuel that has not burned yet (a reached cell waiting
+             * on the threshold included) */
+            while (si < n_seed && seeds[2 * si + 1] * P <= m - 1) {
+                const int32_t c = seeds[2 * si];
+                if (fuel[c] != 0 && arrival[c] == INF_T) {
+                    arrival[c] = seeds[2 * si + 1] * P;
+                    if (nb == cap) {
+                        cap *= 2;
+                        burn = (burning_t*)realloc(burn, sizeof(burning_t) * cap);
+                    }
+                    burn[nb].cell = c;
+                    burn[nb].qperiod = -1;
+                    for (int k = 0; k < 8; ++k) burn[nb].prog[k] = 0;
+                    ++nb;
+                    ++st_ign;
+                }
+                ++si;
+            }
             if (!burning_minute(m, burn_hours)) continue;
             const int32_t p = (m - 1) / P;
             /* sending: every burning cell advances its fire along each axis
@@ -759,6 +808,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
         stats[1] = st_bcm;
         stats[2] = st_fbp;
     }
+    free(seeds);
     free(burn);
     free(pending);
     free(reached);

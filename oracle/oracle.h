@@ -89,7 +89,14 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
  * burn_hours hours of every day counted from the start (0 = no limit);
  * burnout_ros > 0 (m/min) burns a cell out when, at an evaluation of its
  * rates for a period, its integer axis rates toward every in-grid burnable
- * neighbour are below it (assumption A5 (i)): it spreads no further. */
+ * neighbour are below it (assumption A5 (i)): it spreads no further.
+ * ignition_mode 4 takes the ignition-point list of Section 3.2 (iii):
+ * ignition_list holds n_ignitions (cell, period) pairs (0 <= period <
+ * n_periods, any order; entries of one period keep theirs).  The cell of a
+ * pair is lit at minute period * period_min, as a single ignition would be,
+ * if it has fuel and has not burned yet (a reached cell waiting on the
+ * threshold included); ignition_out reports the cell of the earliest entry.
+ * ignition_period is unused in that mode. */
 int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
                         const int16_t* elev, double pc_pct, double curing_pct,
                         int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,
@@ -97,6 +104,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         double sigma, double threshold, int32_t rounding,
                         int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
                         int32_t ignition_period, int32_t burn_hours, double burnout_ros,
+                        int32_t n_ignitions, const int32_t* ignition_list,
                         int32_t scenario_mode, int32_t scenario_fixed,
                         int32_t n_override, const int32_t* override_key, const int32_t* override_q,
                         uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
