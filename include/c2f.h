@@ -167,7 +167,8 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *   ignition_mode  0 = ignition_cell, 1 = uniform over burnable cells,
  *                  2 = the burnable cell nearest (rows/2, cols/2),
  *                  3 = drawn from the landscape's ignition map
- *                  (c2f_set_ignition_map; Section 3.1, uncertainty (1)).
+ *                  (c2f_set_ignition_map; Section 3.1, uncertainty (1)),
+ *                  4 = the ignition-point list below.
  *   scenario_mode  0 = scenario, 1 = uniform over the weather's scenarios.
  *   ignition_period  the fire is lit at the start of this period
  *                  (0 <= ignition_period < n_periods): its cell takes minute
@@ -183,7 +184,19 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *                  off): when a burning cell's rates are evaluated for a
  *                  period and its integer axis rates toward every in-grid
  *                  burnable neighbour are below delta, it spreads no further,
- *                  in that period or later. */
+ *                  in that period or later.
+ *   n_ignitions, ignition_list  the ignition-point input of Section 3.2
+ *                  (iii) for ignition_mode 4: n_ignitions (1..32) pairs
+ *                  (cell, period) (host, copied; 0 <= period < n_periods, any
+ *                  order).  Every replication lights each listed cell at
+ *                  minute period * period_min, as a single ignition at that
+ *                  period would be, if the cell has fuel and has not burned
+ *                  yet (a reached cell waiting on the threshold included),
+ *                  inside or outside the burning window; the run goes on
+ *                  while entries remain.  ignition_period is unused, and the
+ *                  replication's reported ignition is the cell of the
+ *                  earliest entry (the first listed among entries of one
+ *                  period).  Other modes need n_ignitions = 0. */
 typedef struct {
     int32_t landscape_id, weather_id, reps, n_periods;
     uint64_t seed;
@@ -194,6 +207,8 @@ typedef struct {
     int32_t rep_offset;
     int32_t ignition_period, burn_hours;
     float burnout_ros;
+    int32_t n_ignitions;
+    const int32_t* ignition_list;
 } c2f_sim_params;
 
 /* Outputs of a simulation (Section 3.6 (i) burn grids and their counts).

@@ -27,7 +27,8 @@ class SimParams(ctypes.Structure):
                 ("ignition_mode", ctypes.c_int32), ("ignition_cell", ctypes.c_int32),
                 ("scenario_mode", ctypes.c_int32), ("scenario", ctypes.c_int32),
                 ("rep_offset", ctypes.c_int32), ("ignition_period", ctypes.c_int32),
-                ("burn_hours", ctypes.c_int32), ("burnout_ros", ctypes.c_float)]
+                ("burn_hours", ctypes.c_int32), ("burnout_ros", ctypes.c_float),
+                ("n_ignitions", ctypes.c_int32), ("ignition_list", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):

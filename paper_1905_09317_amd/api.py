@@ -47,13 +47,19 @@ class Request:
     burnout: float = 0.0
     outputs: tuple = OUTPUT_NAMES
     device_out: bool = False
+    ignitions: object = None   # (cell, period) pairs: the ignition-point list (ignition_mode 4)
 
     def params(self) -> SimParams:
+        mode, n, ptr = self.ignition_mode, 0, None
+        if self.ignitions is not None:
+            arr = np.ascontiguousarray(self.ignitions, dtype=np.int32).reshape(-1, 2)
+            self._ignition_array = arr   # alive as long as the request
+            mode, n, ptr = 4, arr.shape[0], arr.ctypes.data
         return SimParams(self.landscape, self.weather, self.reps, self.n_periods,
                          int(self.seed) & (2**64 - 1), float(self.sigma), float(self.threshold),
-                         self.rounding, self.precision, self.ignition_mode, self.ignition_cell,
+                         self.rounding, self.precision, mode, self.ignition_cell,
                          self.scenario_mode, self.scenario, self.rep_offset, self.ignition_period,
-                         self.burn_hours, float(self.burnout))
+                         self.burn_hours, float(self.burnout), n, ptr)
 
 
 @dataclass

@@ -143,6 +143,7 @@ struct Exec {
 struct Ticket {
     uint64_t id = 0;
     c2f_sim_params params{};
+    std::vector<int32_t> ign_list;   // the request's ignition-point list, copied
     c2f_outputs out{};
     Landscape* L = nullptr;
     Weather* W = nullptr;
@@ -697,7 +698,22 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, Landscape** L, We
     if (!std::isfinite(p->ros_threshold)) return fail(ctx, C2F_EINVAL, "ros_threshold must be finite");
     if (p->rounding != 0 && p->rounding != 1) return fail(ctx, C2F_EINVAL, "rounding must be 0 or 1");
     if (p->precision != 0 && p->precision != 1) return fail(ctx, C2F_EINVAL, "precision must be 0 or 1");
-    if (p->ignition_mode < 0 || p->ignition_mode > 3) return fail(ctx, C2F_EINVAL, "ignition_mode must be 0..3");
+    if (p->ignition_mode < 0 || p->ignition_mode > 4) return fail(ctx, C2F_EINVAL, "ignition_mode must be 0..4");
+    if (p->ignition_mode == 4) {
+        if (p->n_ignitions < 1 || p->n_ignitions > kMaxIgnitions || !p->ignition_list)
+            return fail(ctx, C2F_EINVAL, "ignition_mode 4 needs 1..%d (cell, period) pairs in ignition_list",
+                        kMaxIgnitions);
+        for (int32_t k = 0; k < p->n_ignitions; ++k) {
+            const int32_t c = p->ignition_list[2 * k], q = p->ignition_list[2 * k + 1];
+            if (c < 0 || c >= l.ncells())
+                return fail(ctx, C2F_EINVAL, "ignition_list entry %d: cell %d outside the grid", k, c);
+            if (q < 0 || q >= p->n_periods)
+                return fail(ctx, C2F_EINVAL, "ignition_list entry %d: period %d not in 0..%d", k, q,
+                            p->n_periods - 1);
+        }
+    } else if (p->n_ignitions != 0) {
+        return fail(ctx, C2F_EINVAL, "n_ignitions > 0 needs ignition_mode 4");
+    }
     if (p->ignition_mode == 3 && !l.ign_cdf)
         return fail(ctx, C2F_EINVAL, "ignition_mode 3 needs an ignition map (c2f_set_ignition_map)");
     if (p->ignition_period < 0 || p->ignition_period >= p->n_periods)
@@ -799,7 +815,8 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     // persistent kernel (the hop chain waits on memory, not on the rate
     // evaluation), so it runs only when asked for.
     const bool split_ok = split_mode == 2 && idx.size() == 1 && p0.ros_sigma == 0.f && p0.rounding == 0 &&
-                          p0.ignition_mode != 3 && p0.ignition_period == 0 && (p0.burn_hours % 24) == 0 &&
+                          p0.ignition_mode != 3 && p0.ignition_mode != 4 && p0.ignition_period == 0 &&
+                          (p0.burn_hours % 24) == 0 &&
                           !(p0.burnout_ros > 0.f) &&
                           p0.scenario_mode == 0 && !(p0.ros_threshold > 0.f) && p0.n_periods <= 4096;
 
@@ -845,6 +862,19 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             j.scen_fixed = p.scenario;
             j.ign_period = p.ignition_period;
             j.ign_cdf = p.ignition_mode == 3 ? L.ign_cdf : nullptr;
+            j.n_seeds = 0;
+            if (p.ignition_mode == 4) {
+                // the list by period; entries of one period keep their order
+                int32_t ord[kMaxIgnitions];
+                for (int32_t k = 0; k < p.n_ignitions; ++k) ord[k] = k;
+                std::stable_sort(ord, ord + p.n_ignitions, [&](int32_t a, int32_t b) {
+                    return p.ignition_list[2 * a + 1] < p.ignition_list[2 * b + 1];
+                });
+                for (int32_t k = 0; k < p.n_ignitions; ++k)
+                    j.seeds[k] = make_int2(p.ignition_list[2 * ord[k]], p.ignition_list[2 * ord[k] + 1]);
+                j.n_seeds = p.n_ignitions;
+                j.ign_period = j.seeds[0].y;
+            }
             j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
             j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
             j.burnout = p.burnout_ros;
@@ -2075,6 +2105,11 @@ c2f_status c2f_submit(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outp
     auto t = std::make_shared<Ticket>();
     t->params = *params;
     t->out = *out;
+    if (params->ignition_mode == 4 && params->ignition_list && params->n_ignitions > 0 &&
+        params->n_ignitions <= kMaxIgnitions) {
+        t->ign_list.assign(params->ignition_list, params->ignition_list + 2 * params->n_ignitions);
+        t->params.ignition_list = t->ign_list.data();
+    }
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         c2f_status st = check_params(ctx, params, &t->L, &t->W);

@@ -431,6 +431,8 @@ __device__ __forceinline__ void rep_draws(const Job& job, uint32_t rep, int& sce
         }
     } else if (job.ign_mode == 2) {
         ign = job.land->centre_cell;
+    } else if (job.ign_mode == 4) {
+        ign = job.n_seeds > 0 ? job.seeds[0].x : -1;   // the earliest entry of the list
     } else if (job.ign_total > 0) {
         const uint4 x = draw(job.seed, 0xFFFFFFFFu, 0xFFFFFFFFu, rep, 3u);
         const uint64_t W = job.ign_total;

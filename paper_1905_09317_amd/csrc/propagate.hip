@@ -185,6 +185,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     __shared__ int s_item, s_flag;
     __shared__ uint32_t s_tag;
     __shared__ int s_scen, s_ign;
+    __shared__ int s_seed;   // next entry of the ignition-point list to light
     __shared__ unsigned long long s_cnt[kNumCounters];
     __shared__ CoefR<R> s_coef[kNumFuels];
     __shared__ CoefR<double> s_coef64[kNumFuels];
@@ -247,6 +248,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             rep_draws(job, rep, scen, ign);
             s_scen = scen;
             s_ign = ign;
+            s_seed = 0;
         }
         __syncthreads();
         if (s_tag <= 1u) {   // tags exhausted: refill this slot's plane
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             s_tag = tag;
             slots.tags[slot] = tag;
             const int ign = s_ign;
-            if (ign >= 0 && rec_fuel(cells[ign].info) != 0) {
+            if (job.ign_mode != 4 && ign >= 0 && rec_fuel(cells[ign].info) != 0) {
                 // the ignition takes the last minute before its period
                 const uint32_t v = (tag << kMinuteBits) | (uint32_t)(job.ign_period * P);
                 plane[ign] = v;
@@ -319,6 +321,32 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         };
 
         for (int p = job.ign_period; p < job.n_periods; ++p) {
+            // list ignitions of period p take minute p P, inside or outside
+            // the burning window, on cells with fuel that have not burned
+            // (a pending cell included).  Lit by one thread between periods,
+            // when no other thread touches the plane or the queue; an
+            // improved label joins the queue like the set-up ignition.
+            if (s_seed < job.n_seeds && job.seeds[s_seed].y <= p) {
+                if (tid == 0) {
+                    int k = s_seed;
+                    for (; k < job.n_seeds && job.seeds[k].y <= p; ++k) {
+                        const uint32_t c = (uint32_t)job.seeds[k].x;
+                        if (rec_fuel(cells[c].info) == 0) continue;
+                        const uint32_t v = (tag << kMinuteBits) | (uint32_t)(job.seeds[k].y * P);
+                        const uint32_t old = atomicMin(&plane[c], v);
+                        if (v < old) {
+                            if ((old >> kMinuteBits) != tag || (old & kMinuteMask) == kPendingMinute) {
+                                ++c_ign;
+                                if (job.count) atomicAdd(&job.count[c], 1u);
+                            }
+                            q_put(s_res, make_uint2(c, v));
+                            s_commit = ++s_res;
+                        }
+                    }
+                    s_seed = k;
+                }
+                __syncthreads();
+            }
             // outside the daily burning window nothing spreads or ignites:
             // the continuations and pending cells wait, unchanged
             if (!burning_period(job, p)) continue;
@@ -581,7 +609,8 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             pc ^= 1;
             __syncthreads();
             if (s_flag) break;
-            if (s_nC[cc] == 0 && s_nP[pc] == 0) break;   // the fire is out
+            // the fire is out and no listed ignition is still to come
+            if (s_nC[cc] == 0 && s_nP[pc] == 0 && s_seed >= job.n_seeds) break;
         }
         if (s_flag && tid == 0) atomicOr(&rc->overflow, 1);
 

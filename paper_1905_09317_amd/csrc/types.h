@@ -57,6 +57,9 @@ struct LandDev {
 };
 
 // One simulation request as the propagation kernel sees it.
+// Entries of an ignition-point list carried by one request.
+constexpr int kMaxIgnitions = 32;
+
 struct Job {
     const CellRec* cells;
     const int32_t* burnable;   // row-major burnable cells
@@ -74,6 +77,10 @@ struct Job {
     uint64_t ign_total;
     int32_t burn_hours;        // daily burning window (0 = always)
     float burnout;             // burn-out rate threshold, m/min (0 = off)
+    // ignition-point list (mode 4): (cell, period) pairs by period; each
+    // cell is lit at minute period * period_min if it has not burned
+    int32_t n_seeds;
+    int2 seeds[kMaxIgnitions];
     uint8_t* scar;             // outputs (device); NULL = not wanted
     int32_t* arr_period;
     int32_t* arr_minute;

@@ -33,7 +33,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(_lib.SimParams) == 4 * 4 + 8 + 4 * 2 + 4 * 9 + 4   # 72, a multiple of 8
+    # 72 bytes up to burnout_ros, then n_ignitions, 4 bytes of padding and the list pointer
+    assert ctypes.sizeof(_lib.SimParams) == 4 * 4 + 8 + 4 * 2 + 4 * 9 + 4 + 4 + 4 + 8   # 88
     assert ctypes.sizeof(_lib.Outputs) == 7 * 8 + 8
     assert ctypes.sizeof(_lib.WeatherRow) == 16
 

@@ -107,20 +107,22 @@ def test_list_order_within_and_across_periods():
 
 
 def test_a_later_fire_joins_after_the_first_has_stopped():
-    """A calm period stops a grass fire on its own; a fire lit after it on a
-    far, unburned cell still burns (the run goes on while entries remain)."""
+    """A fuel break closes the first grass fire in, and it is out hours
+    before the second is lit beyond the break: the run goes on while
+    entries remain, and the second fire still burns."""
     fuel = np.full((40, 40), 2, np.uint8)
     fuel[:, 20] = 0                      # a fuel break splits the grid
     elev = np.zeros((40, 40), np.int16)
-    wx = np.tile(np.array([[90.0, 80.0, 10.0, 90.0]], np.float32), (8, 1))[None]
-    kw = dict(n_periods=8, seed=1)
+    wx = np.tile(np.array([[90.0, 80.0, 10.0, 90.0]], np.float32), (24, 1))[None]
+    kw = dict(n_periods=24, seed=1)
     left = oracle.simulate(fuel, elev, wx, ignitions=[[20 * 40 + 5, 0]], **kw)
-    right = oracle.simulate(fuel, elev, wx, ignitions=[[20 * 40 + 30, 5]], **kw)
-    both = oracle.simulate(fuel, elev, wx, ignitions=[[20 * 40 + 5, 0], [20 * 40 + 30, 5]], **kw)
-    assert left["burned_cells"][0] > 0 and right["burned_cells"][0] > 0
+    right = oracle.simulate(fuel, elev, wx, ignitions=[[20 * 40 + 30, 16]], **kw)
+    both = oracle.simulate(fuel, elev, wx, ignitions=[[20 * 40 + 5, 0], [20 * 40 + 30, 16]], **kw)
+    assert 0 < left["arrival_minute"].max() < 16 * 60 - 60   # out at least an hour before
+    assert right["burned_cells"][0] > 1
     assert both["burned_cells"][0] == left["burned_cells"][0] + right["burned_cells"][0]
     np.testing.assert_array_equal(both["arrival_minute"], _min_arrivals([left, right]))
-    assert both["arrival_minute"][0, 20 * 40 + 30] == 5 * 60
+    assert both["arrival_minute"][0, 20 * 40 + 30] == 16 * 60
 
 
 @pytest.mark.parametrize("bad", [[], [[-1, 0]], [[1600, 0]], [[5, -1]], [[5, 8]]])
