@@ -530,7 +530,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "c2f::propagate_kernel", "kernel_ms": kernel_ms,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_per_cell_update": alg_bytes / (w.reps * w.rows * w.cols * w.n_periods)},
     }
     n_single = args.per_launch if args.per_launch >= 0 else (64 if w.reps > 1 else 0)
     if n_single > 0 and w.reps > 1:
