@@ -56,10 +56,10 @@ struct LandDev {
     float pc_w32, cf32, cell_m32, pad1;
 };
 
-// One simulation request as the propagation kernel sees it.
 // Entries of an ignition-point list carried by one request.
 constexpr int kMaxIgnitions = 32;
 
+// One simulation request as the propagation kernel sees it.
 struct Job {
     const CellRec* cells;
     const int32_t* burnable;   // row-major burnable cells
