@@ -115,3 +115,92 @@ def test_large_8192_64reps_sampled(sim):
     w = inputs.large_landscape(side=8192, reps=64, n_periods=72)
     _sampled_mc(sim, w, (0, 33, 63))
     assert sim.stats()["grid_blocks"] == 64
+
+
+def test_single_fire_2048_fp64_ignition_list_window_burnout():
+    """The 2048^2 x 48 h fire (FP64 rates, one 512-thread group) lit from five
+    listed cells at periods 0 to 30, with a 12 h daily burning window and a
+    burn-out threshold, element by element against the oracle."""
+    w = inputs.single_large_fire(side=2048, n_periods=48, precision=0)
+    rng = np.random.default_rng(41)
+    cells = rng.choice(np.flatnonzero(w.fuel.ravel() != 0), 5, replace=False)
+    seeds = np.stack([cells, [0, 6, 12, 20, 30]], axis=1).astype(np.int32)
+    over = dict(ignitions=seeds, burn_hours=12, burnout=1.0)
+    outs = SINGLE_OUTS + ("arrival_minute",)
+    with Simulator(0) as sim:
+        _say(f"[fullsize] {w.name} fp64, ignition list, window, burn-out")
+        _, _, g = _run(sim, w, outs, **over)
+        st = sim.stats()
+    assert st["grid_blocks"] == 1 and st["block_threads"] == 512
+    ref = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w, **over))
+    assert_same_outputs(g, ref, outs, where="single fire, ignition list")
+    m = np.asarray(g["arrival_minute"])[0]
+    assert (m[seeds[:, 0]] <= seeds[:, 1] * w.period_min).all()
+
+
+def test_batched_mc_1024_2048reps_ignition_map_sampled(sim):
+    """The batched workload with ignitions drawn from a map, lit at period 2,
+    and a burn-out threshold: properties at full size and sampled
+    replications against the oracle."""
+    w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48)
+    rng = np.random.default_rng(43)
+    weights = np.where(w.fuel.ravel() != 0, rng.integers(0, 1000, w.fuel.size), 0).astype(np.uint32)
+    over = dict(ignition_mode=3, ignition_period=2, burnout=2.0)
+    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    sim.set_ignition_map(land, weights)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    _say(f"[fullsize] {w.name}, ignition map")
+    outs = MC_OUTS + ("ignition_cell",)
+    g = sim.simulate(Request(landscape=land, weather=wx, outputs=outs, **request_kwargs(w, **over)))
+    st = sim.stats()
+    assert st["grid_blocks"] == 512 and st["relaunches"] == 0
+    burned = np.asarray(g["burned_cells"])
+    counts = np.asarray(g["burn_count"]).view(np.uint32)
+    assert int(counts.sum(dtype=np.int64)) == int(burned.sum())
+    assert (weights[np.asarray(g["ignition_cell"])] > 0).all()
+    for r in (0, 1023, 2047):
+        _say(f"[fullsize] {w.name}, ignition map: oracle replication {r}")
+        ref = oracle_run(w.fuel, w.elev, w.weather, want_rep_outputs=False, ignition_weights=weights,
+                         **oracle_kwargs(w, reps=1, rep_offset=r, **over))
+        assert int(burned[r]) == int(ref["burned_cells"][0]), f"replication {r}"
+        assert int(np.asarray(g["ignition_cell"])[r]) == int(ref["ignition_cell"][0])
+    sim.unload_landscape(land)
+    sim.unset_weather(wx)
+
+
+def test_treatment_plans_1024_fused_sampled(sim):
+    """Two fuel-treatment plans of the batched landscape (a 3-cell fuel break
+    and 5 % harvested cells each) fused with the untreated landscape in one
+    launch of 3 x 256 replications; sampled replications of each plan against
+    the oracle on the edited grid."""
+    w = inputs.batched_monte_carlo(side=1024, reps=256, n_scenarios=100, n_periods=48)
+    rng = np.random.default_rng(47)
+    base = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    lids, grids = [base], [w.fuel]
+    for _ in range(2):
+        c0 = int(rng.integers(8, w.cols - 11))
+        strip = (np.arange(w.rows)[:, None] * w.cols + np.arange(c0, c0 + 3)[None, :]).ravel()
+        cut = rng.choice(w.rows * w.cols, w.rows * w.cols // 20, replace=False)
+        cells = np.concatenate([strip, cut]).astype(np.int32)
+        lids.append(sim.derive_landscape(base, cells, 0))
+        f = w.fuel.copy().ravel()
+        f[cells] = 0
+        grids.append(f.reshape(w.fuel.shape))
+    _say("[fullsize] treatment plans, fused launch")
+    outs = sim.simulate_batch([Request(landscape=lid, weather=wx, outputs=MC_OUTS, **request_kwargs(w))
+                               for lid in lids])
+    for k, r in ((0, 5), (1, 0), (1, 200), (2, 255)):
+        _say(f"[fullsize] treatment plan {k}: oracle replication {r}")
+        ref = oracle_run(grids[k], w.elev, w.weather, want_rep_outputs=False,
+                         **oracle_kwargs(w, reps=1, rep_offset=r))
+        assert int(np.asarray(outs[k]["burned_cells"])[r]) == int(ref["burned_cells"][0]), (k, r)
+    for k in range(3):
+        c = np.asarray(outs[k]["burn_count"]).view(np.uint32)
+        assert int(c.sum(dtype=np.int64)) == int(np.asarray(outs[k]["burned_cells"]).sum())
+        if k:
+            assert (c.reshape(w.fuel.shape)[grids[k] == 0] == 0).all()   # treated cells never burn
+    for lid in lids[1:]:
+        sim.unload_landscape(lid)
+    sim.unload_landscape(base)
+    sim.unset_weather(wx)
