@@ -417,6 +417,8 @@ def main():
                     help="oracle worker processes for multi-replication workloads "
                          "(default: min(16, host CPUs))")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=-1, choices=[-1, 0, 1],
+                    help="rate precision: 0 FP64, 1 FP32 (default: the workload's)")
     ap.add_argument("--per-launch", type=int, default=-1,
                     help="also time this many replications one per launch (default: 64 for "
                          "multi-replication workloads, 0 = off)")
@@ -455,6 +457,10 @@ def main():
         return
 
     w = make_workload(args.workload)
+    default_precision = w.precision
+    if args.precision >= 0 and args.precision != w.precision:
+        import dataclasses
+        w = dataclasses.replace(w, precision=args.precision)
     print(f"[bench] workload {w.name}: {w.rows}x{w.cols}, reps {w.reps}, periods {w.n_periods}",
           file=sys.stderr, flush=True)
     sim = Simulator(0)
@@ -495,7 +501,8 @@ def main():
     dense = w.reps * n * B_DENSE if ("scar" in dense_outputs(w) and not deferred) else 0
     alg_bytes = B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"] + dense
     traffic = None
-    if w.name in TRAFFIC and TRAFFIC[w.name][0] == kernel_digest():
+    # counters were taken at the workload's own precision
+    if w.name in TRAFFIC and TRAFFIC[w.name][0] == kernel_digest() and w.precision == default_precision:
         traffic = TRAFFIC[w.name][1]
     kernel_ms = sum(kms) / len(kms)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9

@@ -65,18 +65,19 @@ def boundary_case(xu: np.ndarray, x: np.ndarray, tol_rel: float) -> np.ndarray:
 
 
 def fp32_overrides(sim, land, wx, fuel, elev, weather, *, reps, n_periods, seed, sigma, rounding,
-                   scenarios, cell_m=100, pc=50.0, curing=80.0, tol_rel=2e-5, cells=None):
+                   scenarios, cell_m=100, pc=50.0, curing=80.0, tol_rel=2e-5, cells=None, rep_ids=None):
     """Audit FP32 integer rates against the FP64 oracle for every (rep, period)
     (on `cells` only, if given) and return (override keys, q) for the cells
     where they differ; every difference must be a boundary case of the
-    oracle's value."""
+    oracle's value.  Replications are 0..reps-1, or the global indices
+    rep_ids (scenarios[i] belongs to the i-th of them)."""
     keys, qs, n_checked = [], [], 0
     sel = None if cells is None else np.asarray(cells, np.int64)
-    for r in range(reps):
+    for i, r in enumerate(range(reps) if rep_ids is None else rep_ids):
         for p in range(n_periods):
-            g = sim.eval_ros(land, wx, scenario=int(scenarios[r]), period=p, rep=r, seed=seed,
+            g = sim.eval_ros(land, wx, scenario=int(scenarios[i]), period=p, rep=int(r), seed=seed,
                              sigma=sigma, rounding=rounding, precision=1)
-            o = oracle.eval_ros(fuel, elev, weather, cell_m=cell_m, scenario=int(scenarios[r]),
+            o = oracle.eval_ros(fuel, elev, weather, cell_m=cell_m, scenario=int(scenarios[i]),
                                 period=p, rep=r, seed=seed, sigma=np.float32(sigma).item(),
                                 rounding=rounding, pc=pc, curing=curing,
                                 cells=None if sel is None else sel.astype(np.int32))
@@ -87,10 +88,10 @@ def fp32_overrides(sim, land, wx, fuel, elev, weather, *, reps, n_periods, seed,
                 pos = np.nonzero(diff)[0]
                 ok = boundary_case(o["xu8"][pos], o["x8"][pos], tol_rel) | (gq[pos] == o["q8"][pos])
                 assert ok.all(), f"rep {r} period {p}: non-boundary integer-rate mismatch at {pos[~ok.all(axis=1)][:5]}"
-                for i in pos:
-                    c = int(i) if sel is None else int(sel[i])
-                    keys.append((r, p, c))
-                    qs.append(gq[i])
+                for ix in pos:
+                    c = int(ix) if sel is None else int(sel[ix])
+                    keys.append((int(r), p, c))
+                    qs.append(gq[ix])
     k = np.array(keys, np.int32).reshape(-1, 3)
     q = np.array(qs, np.int32).reshape(-1, 8)
     return k, q, n_checked

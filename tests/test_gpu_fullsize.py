@@ -204,3 +204,38 @@ def test_treatment_plans_1024_fused_sampled(sim):
         sim.unload_landscape(lid)
     sim.unload_landscape(base)
     sim.unset_weather(wx)
+
+
+def test_batched_mc_1024_2048reps_fp32_audited_sampled(sim):
+    """The batched workload with FP32 rates (2048 replications in one launch,
+    as `bench.py --workload batched --precision 1` times it).  Sampled
+    replications run again alone must give the same areas; their integer
+    rates are audited on every cell that burns in either precision and its
+    neighbours, and the audited boundary cases replayed into the oracle."""
+    w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48, precision=1)
+    _say(f"[fullsize] {w.name} fp32")
+    land, wx, g = _run(sim, w, MC_OUTS + ("scenario",))
+    st = sim.stats()
+    assert st["relaunches"] == 0
+    burned = np.asarray(g["burned_cells"])
+    scen = np.asarray(g["scenario"])
+    counts = np.asarray(g["burn_count"]).view(np.uint32)
+    assert int(counts.sum(dtype=np.int64)) == int(burned.sum())
+    for r in (0, 1234, 2047):
+        alone = sim.simulate(Request(landscape=land, weather=wx, outputs=("scar", "burned_cells", "scenario"),
+                                     **request_kwargs(w, reps=1, rep_offset=r)))
+        assert int(alone["burned_cells"][0]) == int(burned[r]), f"replication {r} alone"
+        assert int(alone["scenario"][0]) == int(scen[r])
+        ref0 = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w, reps=1, rep_offset=r))
+        burnt = (np.asarray(alone["scar"][0]) | ref0["scar"][0]).reshape(w.rows, w.cols).astype(bool)
+        cells = np.nonzero(dilate(burnt, 1).ravel())[0]
+        _say(f"[fullsize] replication {r}: auditing {cells.size} cells x {w.n_periods} periods")
+        keys, qs, n = fp32_overrides(sim, land, wx, w.fuel, w.elev, w.weather, reps=1, rep_ids=[r],
+                                     n_periods=w.n_periods, seed=w.seed, sigma=w.sigma, rounding=w.rounding,
+                                     scenarios=[int(scen[r])], cells=cells)
+        _say(f"[fullsize] replication {r}: {len(keys)} boundary cases in {n} audited integer rates")
+        ref = oracle_run(w.fuel, w.elev, w.weather, overrides=(keys, qs),
+                         **oracle_kwargs(w, reps=1, rep_offset=r))
+        assert_same_outputs(alone, ref, ("scar", "burned_cells", "scenario"), where=f"fp32 replication {r}")
+    sim.unload_landscape(land)
+    sim.unset_weather(wx)
