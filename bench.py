@@ -345,6 +345,7 @@ def scar_bench(args) -> None:
     """Scar comparison (Section 4 metrics): the 2048^2 x 48 h single fire in
     FP32 against its FP64 run, period by period (48 reference scars of
     4.2M cells resident in HBM)."""
+    import numpy as np
     import torch
 
     from paper_1905_09317_amd import Request, Simulator
@@ -378,7 +379,7 @@ def scar_bench(args) -> None:
     r = res.cpu().numpy()
     m = {"mse": r[:w.n_periods], "ssim": r[w.n_periods:2 * w.n_periods], "delta_norm": float(r[-1])}
     t0 = time.perf_counter()
-    sim.compare_scars(a32, ref, period_min=w.period_min)
+    sync = sim.compare_scars(a32, ref, period_min=w.period_min)
     sync_ms = (time.perf_counter() - t0) * 1e3
     n = w.rows * w.cols
     alg = w.n_periods * n + 4 * n            # every reference scar once, the arrival field once
@@ -393,12 +394,31 @@ def scar_bench(args) -> None:
         "config": {"workload": f"scars-{w.rows}x{w.cols}-{w.n_periods}periods", "periods": w.n_periods,
                    "cells": n},
         "final": {"mse": float(m["mse"][-1]), "ssim": float(m["ssim"][-1]), "delta_norm": m["delta_norm"]},
+        "sync_equals_async": bool(np.array_equal(sync["mse"], m["mse"]) and np.array_equal(sync["ssim"], m["ssim"])),
         "roofline": {"bound": "hbm", "achieved": alg / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": SCAR_TRAFFIC[1] if kernel_digest(SCAR_SOURCES) == SCAR_TRAFFIC[0] else None,
                      "kernel": "c2f::scar_counts_rows_kernel<16> (the whole comparison in one launch)",
                      "kernel_ms": ms, "alg_bytes_per_launch": alg},
     }
+    if not args.no_cpu_baseline:
+        # the FP64 oracle on the same inputs, repeated for about the CPU budget
+        import oracle
+        a_h, r_h = a32.cpu().numpy(), ref.cpu().numpy()
+        runs, t0 = 0, time.perf_counter()
+        while True:
+            o = oracle.scar_metrics(a_h, r_h, period_min=w.period_min)
+            runs += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": runs * w.n_periods * n / dt, "unit": "cell-periods/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"the full comparison {runs} times by the single-threaded FP64 oracle "
+                                          f"in {dt:.1f} s"}
+        line["oracle_equals_gpu"] = bool(np.array_equal(o["mse"], m["mse"]) and
+                                         np.allclose(o["ssim"], m["ssim"], rtol=1e-9, atol=1e-12) and
+                                         o["delta_norm"] == m["delta_norm"])
     print(json.dumps(line), flush=True)
     sim.close()
 
