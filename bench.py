@@ -454,8 +454,8 @@ def main():
                          "many MiB per step (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the simulation of one GPU's share "
-                          "is what is measured (run with --gpus 1)"}))
+        print(json.dumps({"error": "one GPU per run: the measurement covers one GPU's share of the work "
+                          "(run with --gpus 1)"}))
         sys.exit(2)
 
     import torch
