@@ -212,6 +212,9 @@ def served_bench(args) -> None:
     from paper_1905_09317_amd.serve import load_stream, run_stream
 
     st = inputs.served_stream(n_queries=args.queries, rate_per_s=args.rate)
+    if args.precision >= 0:
+        import dataclasses
+        st = dataclasses.replace(st, precision=args.precision)
     print(f"[bench] {st.name}: {len(st.queries)} queries, loading landscapes", file=sys.stderr,
           flush=True)
     sim = Simulator(0)
@@ -234,12 +237,12 @@ def served_bench(args) -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": ["f64", "f32"][st.precision],
         "data": "synthetic",
         "config": {"workload": st.name, "queries": len(st.queries), "rate_per_s": args.rate,
                    "side": [128, 4096], "reps": [1, 256], "n_periods": st.n_periods,
                    "lanes": args.lanes, "ros_sigma": st.sigma, "rounding": "stochastic",
-                   "rate_precision": "fp64", "ignition": "uniform-burnable"},
+                   "rate_precision": ["fp64", "fp32"][st.precision], "ignition": "uniform-burnable"},
         "latency_ms": {"p50": s["latency_ms_p50"], "p99": s["latency_ms_p99"],
                        "mean": s["latency_ms_mean"], "max": s["latency_ms_max"]},
         "queue_ms": {"p50": s["queue_ms_p50"], "p99": s["queue_ms_p99"]},
