@@ -340,8 +340,15 @@ def treatment_bench(args) -> None:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "c2f::propagate_kernel",
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes},
     }
-    print(json.dumps(line), flush=True)
     sim.close()
+    if not args.no_cpu_baseline:
+        # the untreated plan's replications as the bounded sample
+        import dataclasses
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(dataclasses.replace(w, reps=reps), args.cpu_seconds,
+                                            args.cpu_procs or min(16, os.cpu_count() or 1))
+        line["cpu_baseline"]["sample"] += " (the untreated plan)"
+    print(json.dumps(line), flush=True)
 
 
 def scar_bench(args) -> None:
