@@ -259,7 +259,7 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
 c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]);
 
 /* Tuning.  block_threads: threads per work group of the propagation kernel
- * (64..1024, multiple of 64; 0 = automatic).  list_capacity: least number
+ * (one of 64, 128, 256, 512, 768, 1024; 0 = automatic).  list_capacity: least number
  * of entries per per-replication work list (0 = automatic).  A too small
  * capacity is detected and the run repeated with a larger one, so results
  * never change. */

@@ -762,9 +762,11 @@ LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t
             // keeps 512 threads (2 waves per SIMD, 256 VGPRs); at 1024 it
             // would be held to 128 VGPRs and spill (8192^2 x 64 reps: 10.1
             // ms at 512, 12.8 at 256, 18.8 at 1024).  FP32 single fires take
-            // 1024 threads despite a small spill.
+            // 768 threads: 3 waves per SIMD fit the FP32 kernel's 168
+            // VGPRs with a 20-byte spill (2048^2 single fire: 3.97 ms at
+            // 768, 4.02 at 1024, 4.25 at 512).
             if (cells >= (1 << 20) && total_items <= ctx->n_cu)
-                lp.block = (precision == 1 && total_items <= 16) ? 1024 : 512;
+                lp.block = (precision == 1 && total_items <= 16) ? 768 : 512;
             else
                 lp.block = 256;
             lp.cap = default_list_cap(cells, total_items);
@@ -1974,8 +1976,8 @@ c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capa
     if (!ctx) return C2F_EINVAL;
     ApiScope api(ctx);
     if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256 &&
-        block_threads != 512 && block_threads != 1024)
-        return fail(ctx, C2F_EINVAL, "block_threads must be 0 or one of 64,128,256,512,1024");
+        block_threads != 512 && block_threads != 768 && block_threads != 1024)
+        return fail(ctx, C2F_EINVAL, "block_threads must be 0 or one of 64,128,256,512,768,1024");
     if (list_capacity < 0 || list_capacity > ((int64_t)1 << 30))
         return fail(ctx, C2F_EINVAL, "list_capacity out of range");
     std::lock_guard<std::mutex> lk(ctx->tunemu);
@@ -2040,8 +2042,8 @@ c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* rep) {
     if (st == C2F_OK && hw > 0) cap = std::max<int64_t>(1024, std::min<int64_t>(cap, 4 * hw));
     int32_t best_block = 256;
     double best_ms = 1e30;
-    const int blocks[5] = {64, 128, 256, 512, 1024};
-    for (int b = 0; b < 5 && st == C2F_OK; ++b) {
+    const int blocks[6] = {64, 128, 256, 512, 768, 1024};
+    for (int b = 0; b < 6 && st == C2F_OK; ++b) {
         set_over(blocks[b], cap);
         double ms_sum = 0;
         for (int t = 0; t < 2 && st == C2F_OK; ++t) {

@@ -168,8 +168,8 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
 
 // At least 2 waves per SIMD (<= 256 VGPRs).  A tighter bound (4 waves,
 // 128 VGPRs) doubles the resident replications but spills several hundred
-// bytes per lane to scratch in every pass, and measured slower; a 1024-thread
-// group needs 4 waves per SIMD anyway and keeps 128.
+// bytes per lane to scratch in every pass, and measured slower; a 768-thread
+// group needs 3 waves per SIMD (168 VGPRs) and a 1024-thread one 4 (128).
 template <typename R, int BLOCK>
 __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restrict__ jobs, int n_jobs,
                                                           int total_items, Slots slots,
@@ -700,6 +700,7 @@ static hipError_t launch_prop_t(int block, int grid, const Job* jobs, int n_jobs
         case 128: hipLaunchKernelGGL((propagate_kernel<R, 128>), dim3(grid), dim3(128), 0, s, jobs, n_jobs, total, sl, rc); break;
         case 256: hipLaunchKernelGGL((propagate_kernel<R, 256>), dim3(grid), dim3(256), 0, s, jobs, n_jobs, total, sl, rc); break;
         case 512: hipLaunchKernelGGL((propagate_kernel<R, 512>), dim3(grid), dim3(512), 0, s, jobs, n_jobs, total, sl, rc); break;
+        case 768: hipLaunchKernelGGL((propagate_kernel<R, 768>), dim3(grid), dim3(768), 0, s, jobs, n_jobs, total, sl, rc); break;
         case 1024: hipLaunchKernelGGL((propagate_kernel<R, 1024>), dim3(grid), dim3(1024), 0, s, jobs, n_jobs, total, sl, rc); break;
         default: return hipErrorInvalidValue;
     }
@@ -721,6 +722,7 @@ static int occ_t(int block) {
         case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 128>, 128, 0); break;
         case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 256>, 256, 0); break;
         case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 512>, 512, 0); break;
+        case 768: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 768>, 768, 0); break;
         case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, propagate_kernel<R, 1024>, 1024, 0); break;
         default: break;
     }

@@ -204,7 +204,7 @@ def test_period_split_overflow_relaunches_identically(sim):
     assert_same_outputs(g, r, where="split overflow")
 
 
-@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 768, 1024])
 def test_block_size_does_not_change_results(sim, block):
     _say(f"block {block}")
     w = inputs.batched_monte_carlo(side=64, reps=24, n_scenarios=5, n_periods=12)
@@ -376,7 +376,7 @@ def test_autotune_keeps_results(sim):
     sim.autotune(req)
     after = sim.simulate(req)
     st = sim.stats()
-    assert st["block_threads"] in (64, 128, 256, 512, 1024)
+    assert st["block_threads"] in (64, 128, 256, 512, 768, 1024)
     assert_same_outputs(after, {k: np.asarray(v) for k, v in before.items()}, where="after autotune")
     sim.unload_landscape(land)
     sim.unset_weather(x)
