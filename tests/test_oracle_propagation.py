@@ -325,6 +325,23 @@ def test_area_monotone_in_duration_ffmc_and_bui():
     assert all(x <= y for x, y in zip(c, c[1:]))
 
 
+@pytest.mark.parametrize("fuel_code", [2, 4, 7, 12, 13])
+def test_downwind_extent_monotone_in_wind_speed(fuel_code):
+    """With the wind along an axis (from the west, spreading east) the fire's
+    reach along that axis never shrinks as the wind strengthens: the head
+    rate grows with ISI.  (Burned area is not monotone in wind: the head rate
+    saturates while the length-to-breadth ratio keeps growing, so the
+    ellipse, and its cells on 8 axes, can shrink.)"""
+    fuel = np.full((40, 160), fuel_code, np.uint8)
+    ext = []
+    for ws in (0.0, 5.0, 10.0, 15.0, 20.0, 30.0, 40.0, 60.0):
+        wx = inputs.constant_weather(6, 90.0, 80.0, ws, 270.0)
+        m = oracle.simulate(fuel, None, wx, n_periods=6, ignition_cell=20 * 160 + 5)["arrival_minute"][0]
+        ext.append(int(np.flatnonzero(m.reshape(40, 160)[20] >= 0).max()) - 5)
+    assert all(x <= y for x, y in zip(ext, ext[1:])), ext
+    assert ext[-1] > ext[0]
+
+
 def test_arrival_monotone_in_noise_free_multiplier():
     """Raising every axis rate never delays any arrival (the fixed point is
     monotone in q): with the same rounding uniforms, a higher FFMC on flat
