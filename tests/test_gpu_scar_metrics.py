@@ -141,3 +141,18 @@ def test_small_then_large_period_counts_stay_clean():
             _check(s.compare_scars(arr, ref), oracle.scar_metrics(arr, ref))
     finally:
         s.close()
+
+
+def test_full_size_comparison_equals_oracle(sim):
+    """The measured shape: 48 reference scars of 2048^2 cells (16 cells per
+    lane, one group per compute unit), random scars that grow period by
+    period, against the oracle."""
+    import torch
+    _say("scar comparison 2048^2 x 48")
+    n, T = 2048 * 2048, 48
+    rng = np.random.default_rng(2048)
+    arr = np.where(rng.random(n) < 0.6, rng.integers(0, T * 60 + 60, n), -1).astype(np.int32)
+    start = rng.integers(0, T + 8, n)
+    ref = (np.arange(T)[:, None] >= start[None, :]).astype(np.uint8)
+    g = sim.compare_scars(torch.from_numpy(arr).to("cuda:0"), torch.from_numpy(ref).to("cuda:0"))
+    _check(g, oracle.scar_metrics(arr, ref))
