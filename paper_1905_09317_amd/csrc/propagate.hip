@@ -353,8 +353,16 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             const int32_t s = p * P + 1;   // first minute of period p
             const int32_t e = (p + 1) * P; // last minute of period p
 
+            // Each wave counts as a holder of the queue until it has done its
+            // share of the pending cells and continuations below, so that no
+            // wave finds the queue drained while another may still append to
+            // it.  The waves then join the queue without a barrier: a wave
+            // done early takes entries while others still advance
+            // continuations (the labels are a least fixed point, whatever
+            // the order).
+            if (__lane_id() == 0) atomicAdd(&s_hb, 1ull);
             // Pending cells ignite at the start of p if their rate now passes;
-            // the new labels join this period's first round list.
+            // the new labels join this period's queue.
             {
                 const int nP = (int)min((int64_t)s_nP[pc], cap);
                 for (int base = 0; base < nP; base += BLOCK) {
@@ -505,7 +513,6 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             };
 
             // continuations of p-1, advanced from the start of p
-            __syncthreads();
             {
                 const int n = (int)min((int64_t)s_nC[cc], cap);
                 if (n > max_list) max_list = n;
@@ -528,7 +535,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                     process(act, c, lab, rem, true);
                 }
             }
-            __syncthreads();
+            if (__lane_id() == 0) atomicAdd(&s_hb, ~0ull);   // no longer a holder
 
             // label correcting over the period's queue
             for (;;) {
