@@ -65,18 +65,6 @@ __device__ __forceinline__ int wave_reserve(bool pred, int* counter, uint64_t& m
     return lane_value(base, leader) + wave_rank(m);
 }
 
-// Round lists: the first lcap entries in LDS, the rest in the slot's global list.
-__device__ __forceinline__ void append_w(bool pred, uint2 val, uint2* lds, int lcap, uint2* glob, int64_t cap,
-                                         int* counter, int* flag) {
-    uint64_t m;
-    const int idx = wave_reserve(pred, counter, m);
-    if (pred) {
-        if (idx < lcap) lds[idx] = val;
-        else if ((int64_t)(idx - lcap) < cap) glob[idx - lcap] = val;
-        else *flag = 1;
-    }
-}
-
 template <typename T>
 __device__ __forceinline__ void append_g(bool pred, const T& val, T* glob, int64_t cap, int* counter, int* flag) {
     uint64_t m;

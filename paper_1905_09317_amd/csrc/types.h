@@ -98,7 +98,7 @@ struct Cont {
 };
 
 // Global part of a work slot's lists, list_cap entries each:
-//   W[2] round lists (spill beyond the LDS part), uint2 (cell, label)
+//   W    the period queue beyond its LDS part (2 x list_cap entries), uint2 (cell, label)
 //   C[2] continuation lists, Cont
 //   P[2] pending cells, uint32
 constexpr int64_t kSlotListBytesPerEntry = 2 * 8 + 2 * 24 + 2 * 4;
@@ -149,7 +149,7 @@ struct SplitRegion {
 };
 
 enum Counter {
-    kCntEntries = 0,     // round-list entries read
+    kCntEntries = 0,     // queue entries read
     kCntEvals,           // per (cell, period) rate evaluations
     kCntCandidates,      // arrival candidates offered
     kCntImprovements,    // candidates that lowered a label
