@@ -265,15 +265,6 @@ c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]);
  * never change. */
 c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capacity);
 
-/* Period-split launches.  A request whose rates do not depend on the
- * replication (ros_sigma 0, rounding 0, scenario_mode 0, no threshold) can
- * run one weather period at a time, with the integer axis rates of the
- * cells around the fire computed for each period by the whole device
- * before the period is propagated.  mode 0 (default) and 1: never (the
- * persistent kernel, measured as fast on large single fires); 2: whenever
- * the request allows it.  Results are the same either way. */
-c2f_status c2f_set_period_split(c2f_ctx* ctx, int32_t mode);
-
 /* Replication order.  When a launch has more replications than resident
  * work groups, each group runs several one after another, and a long
  * replication taken last keeps its group busy after the others finish.
@@ -302,7 +293,6 @@ typedef struct {
     double kernel_ms;        /* propagation kernel time (HIP events) */
     int32_t block_threads, grid_blocks;
     int64_t list_capacity;
-    int32_t period_split;    /* 1 if the launch ran period by period with precomputed rates */
     int32_t rep_order;       /* 1 if groups took replications longest-predicted first */
 } c2f_run_stats;
 c2f_status c2f_get_stats(const c2f_ctx* ctx, c2f_run_stats* out);

@@ -291,10 +291,6 @@ class Simulator:
     def set_tuning(self, block_threads: int = 0, list_capacity: int = 0):
         self._check(self._L.c2f_set_tuning(self._ctx, int(block_threads), int(list_capacity)))
 
-    def set_period_split(self, mode: int = 0):
-        """0 or 1: never; 2: whenever the request allows it (same results)."""
-        self._check(self._L.c2f_set_period_split(self._ctx, int(mode)))
-
     def set_rep_order(self, mode: int = 1):
         """1: work groups that run several replications take the longest
         predicted first (default); 0: in index order.  Same results."""

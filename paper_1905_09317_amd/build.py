@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libc2f.so")
-SOURCES = ["prep.hip", "propagate.hip", "split.hip", "order.hip", "metrics.hip", "capi.cpp"]
+SOURCES = ["prep.hip", "propagate.hip", "order.hip", "metrics.hip", "capi.cpp"]
 HEADERS = ["device.h", "fuel_table.h", "kernels.h", "ln64.h", "types.h"]
 
 HIPCC_FLAGS = [
@@ -36,14 +36,19 @@ def build(verbose: bool = False) -> str:
     objs = []
     env = dict(os.environ)
     env.setdefault("TMPDIR", "/tmp")
+    procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
         cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
-        subprocess.run(cmd, check=True, env=env, cwd=objdir)
+        # the sources compile independently: one compiler process each
+        procs.append((src, subprocess.Popen(cmd, env=env, cwd=objdir)))
         objs.append(obj)
+    failed = [src for src, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, f"hipcc {' '.join(failed)}")
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:

@@ -124,11 +124,6 @@ struct Exec {
     unsigned long long* order_keys = nullptr;   // replication order: a key
     int32_t* order = nullptr;                   // and a position per item
     int32_t order_cap = 0;
-    SplitState* split_st = nullptr;   // period-split launches: state per slot,
-    int32_t split_st_cap = 0;
-    SplitRegion* split_reg = nullptr; // the shared region record,
-    uint4* rate_cache = nullptr;      // and precomputed rates per cell
-    int64_t rate_cache_cells = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     c2f_run_stats last{};
@@ -195,7 +190,6 @@ struct c2f_ctx {
     size_t bytes_in_use = 0;
 
     std::mutex tunemu;
-    int32_t split_mode = 0;   // period-split launches: 0/1 never, 2 whenever possible
     int32_t rep_order = 1;    // 1: longest predicted replications first when groups run several
     int32_t block_override = 0;
     int64_t cap_override = 0;
@@ -346,14 +340,6 @@ void exec_trim(c2f_ctx* ctx, Exec& ex) {
     ex.order_keys = nullptr;
     ex.order = nullptr;
     ex.order_cap = 0;
-    dev_free(ctx, ex.split_st, (size_t)ex.split_st_cap * sizeof(SplitState));
-    dev_free(ctx, ex.split_reg, sizeof(SplitRegion));
-    dev_free(ctx, ex.rate_cache, (size_t)ex.rate_cache_cells * sizeof(uint4));
-    ex.split_st = nullptr;
-    ex.split_st_cap = 0;
-    ex.split_reg = nullptr;
-    ex.rate_cache = nullptr;
-    ex.rate_cache_cells = 0;
     ex.planes = nullptr;
     ex.n_slots = 0;
     ex.plane_cells = 0;
@@ -612,35 +598,6 @@ c2f_status ensure_order(c2f_ctx* ctx, Exec& ex, int32_t n) {
     return C2F_OK;
 }
 
-c2f_status ensure_split(c2f_ctx* ctx, Exec& ex, int32_t n, int64_t cells) {
-    if (n > ex.split_st_cap) {
-        drop_graph(ex);
-        dev_free(ctx, ex.split_st, (size_t)ex.split_st_cap * sizeof(SplitState));
-        ex.split_st = nullptr;
-        ex.split_st_cap = 0;
-        const int32_t cap = (int32_t)pow2_at_least(std::max(n, 64));
-        c2f_status st = dev_alloc(ctx, (void**)&ex.split_st, (size_t)cap * sizeof(SplitState));
-        if (st != C2F_OK) return st;
-        ex.split_st_cap = cap;
-    }
-    if (!ex.split_reg) {
-        drop_graph(ex);
-        c2f_status st = dev_alloc(ctx, (void**)&ex.split_reg, sizeof(SplitRegion));
-        if (st != C2F_OK) return st;
-    }
-    if (cells > ex.rate_cache_cells) {
-        drop_graph(ex);
-        dev_free(ctx, ex.rate_cache, (size_t)ex.rate_cache_cells * sizeof(uint4));
-        ex.rate_cache = nullptr;
-        ex.rate_cache_cells = 0;
-        const int64_t nc = ex.round_up ? pow2_at_least(cells) : cells;
-        c2f_status st = dev_alloc(ctx, (void**)&ex.rate_cache, (size_t)nc * sizeof(uint4));
-        if (st != C2F_OK) return st;
-        ex.rate_cache_cells = nc;
-    }
-    return C2F_OK;
-}
-
 c2f_status ensure_staging(c2f_ctx* ctx, Exec& ex, size_t bytes) {
     if (bytes > ex.staging_bytes) {
         drop_graph(ex);
@@ -802,26 +759,13 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
     if (st != C2F_OK) return st;
     bool dense = false;
     for (int k : idx) dense |= plans[k].scar || plans[k].arr_minute || plans[k].arr_period;
-    int32_t split_mode, rep_order;
+    int32_t rep_order;
     {
         std::lock_guard<std::mutex> lk(ctx->tunemu);
-        split_mode = ctx->split_mode;
         rep_order = ctx->rep_order;
     }
     int32_t max_periods = 0;
     for (int k : idx) max_periods = std::max(max_periods, P[k].n_periods);
-    // Period-split form: one request whose rates do not depend on the
-    // replication (no noise, nearest rounding, one scenario, no threshold).
-    const c2f_sim_params& p0 = P[idx[0]];
-    // Measured on the 2048^2 single fire it is not faster than the
-    // persistent kernel (the hop chain waits on memory, not on the rate
-    // evaluation), so it runs only when asked for.
-    const bool split_ok = split_mode == 2 && idx.size() == 1 && p0.ros_sigma == 0.f && p0.rounding == 0 &&
-                          p0.ignition_mode != 3 && p0.ignition_mode != 4 && p0.ignition_period == 0 &&
-                          (p0.burn_hours % 24) == 0 &&
-                          !(p0.burnout_ros > 0.f) &&
-                          p0.scenario_mode == 0 && !(p0.ros_threshold > 0.f) && p0.n_periods <= 4096;
-
     for (;;) {
         st = ensure_slots(ctx, ex, lp.grid, max_cells, lp.cap);
         if (st == C2F_ENOMEM && lp.grid > 1) {
@@ -897,24 +841,15 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
                                     ex.stream));
 
         // dense outputs by a grid-wide kernel when no slot runs two items
-        const bool split = split_ok && total <= lp.grid && total <= 65535;
         const bool defer = dense && total <= lp.grid && total <= 65535;
         if (defer) {
             st = ensure_item_slots(ctx, ex, total);
             if (st != C2F_OK) return st;
         }
         // groups that run several replications take the longest predicted first
-        const bool ordered = rep_order == 1 && !split && total > lp.grid && max_periods <= 65535;
+        const bool ordered = rep_order == 1 && total > lp.grid && max_periods <= 65535;
         if (ordered) {
             st = ensure_order(ctx, ex, total);
-            if (st != C2F_OK) return st;
-        }
-        if (split) {
-            st = ensure_split(ctx, ex, total, max_cells);
-            if (st == C2F_ENOMEM && lp.grid > 1) {
-                lp.grid = std::max(1, lp.grid / 2);
-                continue;
-            }
             if (st != C2F_OK) return st;
         }
         const int64_t limit = std::min(lp.cap, ex.list_cap);
@@ -926,8 +861,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
                                      (uint64_t)(uintptr_t)ex.planes, (uint64_t)(uintptr_t)ex.lists,
                                      (uint64_t)ex.list_cap, (uint64_t)limit, (uint64_t)ex.plane_cells,
                                      (uint64_t)(uintptr_t)ex.stream, (uint64_t)defer,
-                                     (uint64_t)(uintptr_t)ex.item_slot, (uint64_t)split,
-                                     (uint64_t)(uintptr_t)ex.split_st, (uint64_t)(uintptr_t)ex.rate_cache,
+                                     (uint64_t)(uintptr_t)ex.item_slot,
                                      (uint64_t)P[idx[0]].n_periods, (uint64_t)ordered,
                                      (uint64_t)(uintptr_t)ex.order_keys, (uint64_t)max_periods};
         for (int k : idx) {
@@ -954,11 +888,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
                                  ex.stream);
                 if (e != hipSuccess) return e;
             }
-            if (split)
-                e = launch_split(precision, lp.block, ex.d_jobs, total, P[idx[0]].n_periods, 4 * ctx->n_cu, sl,
-                                 ex.split_st, ex.split_reg, ex.rate_cache, ex.rc, ex.stream);
-            else
-                e = launch_propagate(precision, lp.block, lp.grid, ex.d_jobs, (int)idx.size(), total, sl, ex.rc,
+            e = launch_propagate(precision, lp.block, lp.grid, ex.d_jobs, (int)idx.size(), total, sl, ex.rc,
                                      ex.stream);
             if (e != hipSuccess || !defer) return e;
             return launch_dense_outputs(ex.d_jobs, (int)idx.size(), total, lp.grid, max_cells, sl, ex.rc,
@@ -1014,7 +944,6 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             ex.last.block_threads = lp.block;
             ex.last.grid_blocks = lp.grid;
             ex.last.list_capacity = limit;
-            ex.last.period_split = split ? 1 : 0;
             ex.last.rep_order = ordered ? 1 : 0;
             return C2F_OK;
         }
@@ -1173,13 +1102,6 @@ size_t batch_growth(c2f_ctx* ctx, const Exec& ex, const std::vector<std::shared_
     const int32_t n_items = std::max(items[0], items[1]);
     if (n_items > grid && n_items > ex.order_cap)   // a launch in replication order
         g += ((size_t)pow2_at_least(std::max(n_items, 64)) - (size_t)ex.order_cap) * kOrderBytesPerItem;
-    bool split_possible;
-    {
-        std::lock_guard<std::mutex> lk(ctx->tunemu);
-        split_possible = ctx->split_mode == 2;
-    }
-    if (split_possible && batch.size() == 1 && max_cells > ex.rate_cache_cells)   // a possible period-split launch
-        g += (size_t)((ex.round_up ? pow2_at_least(max_cells) : max_cells) - ex.rate_cache_cells) * sizeof(uint4);
     return g;
 }
 
@@ -1983,15 +1905,6 @@ c2f_status c2f_set_tuning(c2f_ctx* ctx, int32_t block_threads, int64_t list_capa
     std::lock_guard<std::mutex> lk(ctx->tunemu);
     ctx->block_override = block_threads;
     ctx->cap_override = list_capacity;
-    return C2F_OK;
-}
-
-c2f_status c2f_set_period_split(c2f_ctx* ctx, int32_t mode) {
-    if (!ctx) return C2F_EINVAL;
-    ApiScope api(ctx);
-    if (mode < 0 || mode > 2) return fail(ctx, C2F_EINVAL, "mode must be 0, 1 or 2");
-    std::lock_guard<std::mutex> lk(ctx->tunemu);
-    ctx->split_mode = mode;
     return C2F_OK;
 }
 

@@ -458,6 +458,13 @@ __device__ __forceinline__ bool burning_period(const Job& job, int p) {
     return (int)(((int64_t)p * job.period_min) % 1440) < job.burn_hours * 60;
 }
 
+// Does the ignition-point list hold an entry of period p?
+__device__ __forceinline__ bool seeds_at(const Job& job, int p) {
+    for (int k = 0; k < job.n_seeds; ++k)
+        if (job.seeds[k].y == p) return true;
+    return false;
+}
+
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
 // the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.
 template <typename R>

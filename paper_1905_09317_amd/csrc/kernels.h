@@ -41,15 +41,6 @@ hipError_t launch_propagate(int precision, int block, int grid, const Job* jobs,
                             const Slots& slots, RunCounters* rc, hipStream_t s);
 int propagate_blocks_per_cu(int precision, int block);
 
-// Period-split launch of one job whose rates do not depend on the
-// replication: set-up, then per period a rate kernel over the rectangle
-// around the fire (rate_blocks x 256 threads) and the period kernel (one
-// group of `block` threads per item, item i in slot i), then the
-// per-replication outputs.  st[total], one SplitRegion, cache[rows*cols].
-hipError_t launch_split(int precision, int block, const Job* jobs, int total, int n_periods, int rate_blocks,
-                        const Slots& slots, SplitState* st, SplitRegion* reg, uint4* cache, RunCounters* rc,
-                        hipStream_t s);
-
 // Replication order of a launch whose work groups each run several items:
 // keys[item] = predicted head-fire travel (zeroed first), order = items by
 // decreasing key.  max_periods <= 65535.

@@ -173,7 +173,12 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     __shared__ int s_item, s_flag;
     __shared__ uint32_t s_tag;
     __shared__ int s_scen, s_ign;
-    __shared__ int s_seed;   // next entry of the ignition-point list to light
+    // Decisions that steer every wave through the same barriers.  Each is
+    // written by thread 0 only between two barriers and read by all
+    // threads after the second, so no wave can read a value meant for a
+    // later step: s_refill (the slot's plane needs refilling) and s_stop
+    // (leave the period loop after this period).
+    __shared__ int s_refill, s_stop;
     __shared__ unsigned long long s_cnt[kNumCounters];
     __shared__ CoefR<R> s_coef[kNumFuels];
     __shared__ CoefR<double> s_coef64[kNumFuels];
@@ -192,7 +197,11 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     Cont* const gC[2] = {(Cont*)(lb + 16 * stride), (Cont*)(lb + 16 * stride) + stride};
     uint32_t* const gP[2] = {(uint32_t*)(lb + 64 * stride), (uint32_t*)(lb + 64 * stride) + stride};
 
-    for (;;) {
+    for (int taken = 0;; ++taken) {
+        // With deferred dense outputs (item_slot set) a slot's plane must
+        // still hold its item's labels when the launch ends, so a group runs
+        // at most one item; the launch then has a group for every item.
+        if (slots.item_slot && taken > 0) break;
         if (tid == 0) {
             int it = atomicAdd(&rc->next_item, 1);
             if (__hip_atomic_load(&rc->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = total_items;
@@ -226,23 +235,23 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
 
         // ------------------------------------------- replication set-up
         if (tid == 0) {
-            s_tag = slots.tags[slot];   // previous tag; refilled below if exhausted
+            const uint32_t prev = slots.tags[slot];
+            s_refill = prev <= 1u;   // tags exhausted: refill this slot's plane
+            s_tag = prev <= 1u ? kTagFresh : prev;
             s_res = s_commit = 0;
             s_hb = 0ull;
             s_nC[0] = s_nC[1] = s_nP[0] = s_nP[1] = 0;
             s_flag = 0;
+            s_stop = 0;
             for (int k = 0; k < kNumCounters; ++k) s_cnt[k] = 0;
             int scen, ign;
             rep_draws(job, rep, scen, ign);
             s_scen = scen;
             s_ign = ign;
-            s_seed = 0;
         }
         __syncthreads();
-        if (s_tag <= 1u) {   // tags exhausted: refill this slot's plane
+        if (s_refill) {
             for (size_t i = tid; i < (size_t)slots.plane_cells; i += BLOCK) plane[i] = kPlaneFill;
-            __syncthreads();
-            if (tid == 0) s_tag = kTagFresh;
             __syncthreads();
         }
         if (tid == 0) {
@@ -308,16 +317,21 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             q_commit(wbase, (int)__popcll(m));
         };
 
+        // the list's entries are sorted by period and the loop starts at the
+        // earliest, so the entries of period p are those with period p, and
+        // none is still to come after the last entry's period: both follow
+        // from p alone, which every thread knows
+        const int last_seed_period = job.n_seeds > 0 ? job.seeds[job.n_seeds - 1].y : -1;
         for (int p = job.ign_period; p < job.n_periods; ++p) {
             // list ignitions of period p take minute p P, inside or outside
             // the burning window, on cells with fuel that have not burned
             // (a pending cell included).  Lit by one thread between periods,
             // when no other thread touches the plane or the queue; an
             // improved label joins the queue like the set-up ignition.
-            if (s_seed < job.n_seeds && job.seeds[s_seed].y <= p) {
+            if (p <= last_seed_period && seeds_at(job, p)) {
                 if (tid == 0) {
-                    int k = s_seed;
-                    for (; k < job.n_seeds && job.seeds[k].y <= p; ++k) {
+                    for (int k = 0; k < job.n_seeds; ++k) {
+                        if (job.seeds[k].y != p) continue;
                         const uint32_t c = (uint32_t)job.seeds[k].x;
                         if (rec_fuel(cells[c].info) == 0) continue;
                         const uint32_t v = (tag << kMinuteBits) | (uint32_t)(job.seeds[k].y * P);
@@ -331,7 +345,6 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                             s_commit = ++s_res;
                         }
                     }
-                    s_seed = k;
                 }
                 __syncthreads();
             }
@@ -593,8 +606,14 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                 if (n > max_list) max_list = n;
             }
             // ------------------------------------------------- period end
+            // Thread 0 decides whether to stop between the two barriers: a
+            // list overflowed, or the fire is out (no continuation and no
+            // pending cell for p+1) and no listed ignition is still to
+            // come.  Reading s_flag or the list lengths after the second
+            // barrier could see values a faster wave already wrote in p+1.
             __syncthreads();
             if (tid == 0) {
+                s_stop = s_flag || (s_nC[cc ^ 1] == 0 && s_nP[pc ^ 1] == 0 && last_seed_period <= p);
                 s_nC[cc] = 0;
                 s_nP[pc] = 0;
                 s_res = s_commit = 0;
@@ -603,9 +622,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             cc ^= 1;
             pc ^= 1;
             __syncthreads();
-            if (s_flag) break;
-            // the fire is out and no listed ignition is still to come
-            if (s_nC[cc] == 0 && s_nP[pc] == 0 && s_seed >= job.n_seeds) break;
+            if (s_stop) break;
         }
         if (s_flag && tid == 0) atomicOr(&rc->overflow, 1);
 

@@ -126,28 +126,6 @@ struct Slots {
     const int32_t* order;
 };
 
-// Period-split launches (rates that do not depend on the replication):
-// per-slot replication state kept between the per-period kernels.
-struct SplitState {
-    uint32_t tag;
-    int32_t cc;         // current continuation list (0/1)
-    int32_t nC;         // its length
-    int32_t done;       // fire out or overflow: later periods skip the slot
-    int32_t flag;       // a list overflowed
-    int32_t scen, ign, max_list;
-    uint32_t cnt[8];    // entries, conts, evals, candidates, improvements, ignitions, chunks, -
-};
-
-// Shared by all slots of a period-split launch: the bounding box of every
-// cell ignited so far, the largest axis rate of the last two periods, and
-// the rectangle whose rates are precomputed for the current period.
-struct SplitRegion {
-    int32_t r0, r1, c0, c1;
-    int32_t max_q[2];
-    int32_t cr0, cr1, cc0, cc1;
-    int32_t pad[2];
-};
-
 enum Counter {
     kCntEntries = 0,     // queue entries read
     kCntEvals,           // per (cell, period) rate evaluations

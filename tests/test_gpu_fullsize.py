@@ -48,17 +48,6 @@ def test_single_fire_2048_fp64_full():
     assert int(g["burned_cells"][0]) > 10000
 
 
-def test_single_fire_2048_fp64_full_period_split():
-    w = inputs.single_large_fire(side=2048, n_periods=48, precision=0)
-    with Simulator(0) as sim:
-        _say(f"[fullsize] {w.name} fp64, period split")
-        sim.set_period_split(2)
-        _, _, g = _run(sim, w, SINGLE_OUTS)
-        assert sim.stats()["period_split"] == 1
-    ref = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w))
-    assert_same_outputs(g, ref, SINGLE_OUTS, where="single fire fp64 split")
-
-
 def test_single_fire_2048_fp32_full_with_audited_rates():
     """The bench's single-fire workload (FP32 rates).  Integer rates are
     audited on every cell that burns in either run and its neighbours, for

@@ -154,56 +154,6 @@ def test_random_heterogeneous_grids(sim, seed):
     assert_same_outputs(g, r, where=f"seed {seed}")
 
 
-@pytest.mark.parametrize("seed", range(6))
-def test_period_split_equals_oracle_and_persistent(sim, seed):
-    """Rates that do not depend on the replication (no noise, nearest
-    rounding, one scenario, no threshold) run period by period with rates
-    precomputed around the fire; results equal the persistent form and the
-    oracle, with dense outputs, several replications and short periods."""
-    P = [60, 7, 30, 1, 13, 60][seed]
-    block = [256, 64, 1024, 128, 512, 256][seed]
-    _say(f"period split seed={seed} P={P} block={block}")
-    fuel, elev, wx = _random_case(100 + seed, 41, 53, n_periods=10)
-    kw = dict(n_periods=10, reps=[1, 3, 1, 5, 2, 4][seed], seed=77 + seed, sigma=0.0, rounding=0,
-              threshold=0.0, ignition_mode=[2, 1, 0, 1, 2, 1][seed], ignition_cell=41 * 53 // 3,
-              scenario_mode=0, scenario=seed % 3, precision=seed % 2)
-    sim.set_period_split(2)
-    try:
-        land = sim.load_landscape(fuel, elev)
-        w = sim.set_weather(wx, period_min=P)
-        sim.set_tuning(block, 0)
-        g = sim.simulate(Request(landscape=land, weather=w, **kw))
-        assert sim.stats()["period_split"] == 1
-        sim.set_period_split(1)
-        g1 = sim.simulate(Request(landscape=land, weather=w, **kw))
-        assert sim.stats()["period_split"] == 0
-    finally:
-        sim.set_period_split(0)
-        sim.set_tuning(0, 0)
-    assert_same_outputs(g, {k: np.asarray(v) for k, v in g1.items()}, where=f"split vs persistent {seed}")
-    if kw["precision"] == 0:
-        okw = {k: v for k, v in kw.items() if k != "precision"}
-        r = oracle_run(fuel, elev, wx, period_min=P, **okw)
-        assert_same_outputs(g, r, where=f"split vs oracle {seed}")
-    sim.unload_landscape(land)
-    sim.unset_weather(w)
-
-
-def test_period_split_overflow_relaunches_identically(sim):
-    _say("period split overflow")
-    fuel, elev, wx = _random_case(7, 64, 64, n_periods=8)
-    kw = dict(n_periods=8, reps=2, seed=5, sigma=0.0, rounding=0, ignition_mode=1, scenario_mode=0,
-              precision=0)
-    sim.set_period_split(2)
-    try:
-        g, r = _run_both(sim, fuel, elev, wx, cap=1, **kw)
-        st = sim.stats()
-    finally:
-        sim.set_period_split(0)
-    assert st["period_split"] == 1 and st["relaunches"] >= 1
-    assert_same_outputs(g, r, where="split overflow")
-
-
 @pytest.mark.parametrize("block", [64, 128, 256, 512, 768, 1024])
 def test_block_size_does_not_change_results(sim, block):
     _say(f"block {block}")
