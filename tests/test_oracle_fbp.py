@@ -228,3 +228,70 @@ def test_eval_ros_cell_subset_equals_full_grid():
         assert np.array_equal(full[k][cells], sub[k]), k
     with pytest.raises(ValueError):
         oracle.eval_ros(w.fuel, w.elev, w.weather, cells=np.array([48 * 48], np.int32))
+
+
+# ------------------------------------------------ steep slopes, fast fuels
+# Published curve constants (a, b, c, q, BUI0) typed here for the closed
+# forms below: C-2 and S-3.
+_C2 = (110.0, 0.0282, 1.5, 0.70, 64.0)
+_S3 = (55.0, 0.0829, 3.2, 0.75, 31.0)
+
+
+def _ff(ffmc):
+    m = 147.2 * (101.0 - ffmc) / (59.5 + ffmc)
+    return 91.9 * math.exp(-0.1386 * m) * (1.0 + m ** 5.31 / 4.93e7)
+
+
+def _be(k, bui):
+    return math.exp(50.0 * math.log(k[3]) * (1.0 / bui - 1.0 / k[4]))
+
+
+def test_slope_wind_above_40_kmh_keeps_the_slope_identity():
+    """C-2, FFMC 94, 80 % slope, no wind: the slope-equivalent wind exceeds 40
+    km/h, where f(W) = 12 (1 - exp(-0.0818 (W - 28))) and WSE = 28 -
+    ln(1 - ISF / (2.496 f(F))) / 0.0818.  Because 0.208 x 12 = 2.496, the
+    spread index at that wind is ISF again, so H = SF x H_flat still holds
+    and the fire heads upslope at WSV = WSE."""
+    flat = oracle.fbp_point(2, 94.0, 80.0, 0.0, 0.0)
+    r = oracle.fbp_point(2, 94.0, 80.0, 0.0, 0.0, slope_pct=80.0, upslope_az=30.0)
+    assert 40.0 < r["wse"] < 112.45
+    assert r["wsv"] == pytest.approx(r["wse"], rel=1e-14)
+    assert r["hros"] == pytest.approx(10.0 * flat["hros"], rel=1e-11)
+    assert r["raz"] == pytest.approx(30.0, abs=1e-9)
+    # the branch's own closed form, from the zero-wind rate inverted by hand
+    a, b, c, _, _ = _C2
+    ff = _ff(94.0)
+    rsz = a * (-math.expm1(-b * 0.208 * ff)) ** c
+    isf = math.log(1.0 - (10.0 * rsz / a) ** (1.0 / c)) / -b
+    assert r["isi"] == pytest.approx(isf, rel=1e-11)
+    assert r["wse"] == pytest.approx(28.0 - math.log(1.0 - isf / (2.496 * ff)) / 0.0818, rel=1e-11)
+
+
+def test_slope_wind_cap_at_112_45_kmh():
+    """C-2, FFMC 96, 80 % slope: ISF reaches 0.999 x 2.496 f(F), so WSE is
+    capped at 112.45 km/h and H follows from that wind, below SF x H_flat."""
+    a, b, c, _, _ = _C2
+    ff = _ff(96.0)
+    r = oracle.fbp_point(2, 96.0, 80.0, 0.0, 0.0, slope_pct=80.0, upslope_az=200.0)
+    assert r["wse"] == 112.45 and r["wsv"] == pytest.approx(112.45, rel=1e-14)
+    isi = 0.208 * 12.0 * (-math.expm1(-0.0818 * (112.45 - 28.0))) * ff
+    assert r["isi"] == pytest.approx(isi, rel=1e-12)
+    h = a * (-math.expm1(-b * isi)) ** c * _be(_C2, 80.0)
+    assert r["hros"] == pytest.approx(h, rel=1e-12)
+    assert r["hros"] < 10.0 * oracle.fbp_point(2, 96.0, 80.0, 0.0, 0.0)["hros"]
+
+
+def test_isf_floor_inside_the_logarithm():
+    """S-3, FFMC 96, 80 % slope: 1 - (RSF/a)^(1/c) falls below 0.01, so ISF
+    = ln(0.01) / -b and the head rate is a (1 - 0.01)^c BE; WSE stays below
+    40 km/h, on the ordinary branch."""
+    a, b, c, _, _ = _S3
+    ff = _ff(96.0)
+    rsz = a * (-math.expm1(-b * 0.208 * ff)) ** c
+    assert 1.0 - (10.0 * rsz / a) ** (1.0 / c) < 0.01
+    r = oracle.fbp_point(13, 96.0, 80.0, 0.0, 0.0, slope_pct=80.0, upslope_az=90.0)
+    isf = math.log(0.01) / -b
+    assert r["isi"] == pytest.approx(isf, rel=1e-12)
+    assert r["wse"] == pytest.approx(math.log(isf / (0.208 * ff)) / 0.05039, rel=1e-12)
+    assert r["wse"] < 40.0
+    assert r["hros"] == pytest.approx(a * 0.99 ** c * _be(_S3, 80.0), rel=1e-12)
