@@ -242,6 +242,26 @@ c2f_status c2f_simulate(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_ou
 c2f_status c2f_simulate_batch(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params* params,
                               const c2f_outputs* out);
 
+/* c2f_simulate for callers that cannot allocate device memory (code that
+ * runs while a HIP graph is being captured, tight serving loops, hosts that
+ * forbid allocation after start-up).  It calls no hipMalloc, hipFree or
+ * other allocating routine: the launch's counters, job record, generation
+ * tags, arrival planes and work lists live in a fixed device scratch array
+ * of 128 MiB that the library's code object holds on every device it runs
+ * on until the process ends (its address is resolved once per device by
+ * c2f_create).  Outputs must be device pointers (out->on_device = 1), written
+ * in order on the context's stream; the call returns once they are complete.
+ * Results equal c2f_simulate's for the same request.  EINVAL if one work
+ * slot (an arrival plane of 4 B per cell plus its work lists) does not fit
+ * the scratch; the request then needs c2f_simulate.  Fewer resident work
+ * groups than c2f_simulate may run when the scratch holds fewer slots, and
+ * work lists start small and grow on overflow (ECAPACITY past the largest
+ * size that fits), which changes no result.  The scratch keeps whatever the
+ * last call left in it; each call first resets the state it reads.  Calls
+ * on one device share the scratch: the library serialises them within a
+ * process, and calls that overlapped on one device would race. */
+c2f_status c2f_simulate_noalloc(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out);
+
 /* Parity/debug: the per-cell FBP field of one (scenario, period, rep) on the
  * landscape, exactly as the simulation computes it.  Host outputs, any may
  * be NULL, each [rows*cols] (q8 and x8: [rows*cols][8]):

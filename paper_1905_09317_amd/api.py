@@ -262,6 +262,20 @@ class Simulator:
         self._check(self._L.c2f_simulate(self._ctx, ctypes.byref(p), ctypes.byref(o)))
         return res
 
+    def simulate_noalloc(self, req: Request | None = None, **kw) -> dict:
+        """simulate() through c2f_simulate_noalloc: device outputs only, no
+        device allocation inside the library (the outputs are torch tensors
+        allocated here, before the call)."""
+        req = req or Request(**kw)
+        if not req.device_out:
+            raise ValueError("simulate_noalloc needs device outputs (device_out=True)")
+        import torch
+        self.set_stream(torch.cuda.current_stream(self._device))
+        res, o = self._alloc_outputs(req)
+        p = req.params()
+        self._check(self._L.c2f_simulate_noalloc(self._ctx, ctypes.byref(p), ctypes.byref(o)))
+        return res
+
     def simulate_batch(self, reqs: list[Request]) -> list[dict]:
         """Run several requests (any landscapes/weather) in one fused launch."""
         if any(r.device_out for r in reqs):

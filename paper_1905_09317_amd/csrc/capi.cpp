@@ -169,6 +169,7 @@ struct c2f_ctx {
     size_t lane_list_budget = 0;    // list pool of one serving lane
     int n_cu = 0;
     std::chrono::steady_clock::time_point t0;
+    void* scratch = nullptr;    // device address of the no-allocation scratch on `device`
 
     std::mutex errmu;
     std::string err;
@@ -738,6 +739,66 @@ LaunchPlan plan_launch(c2f_ctx* ctx, int64_t cells, int32_t total_items, int32_t
     return lp;
 }
 
+// The kernel's record of one request: landscape and weather on the device,
+// options, and where its outputs go.  Items item_base .. item_base + reps - 1
+// of the launch are its replications.
+Job make_job(const c2f_sim_params& p, const Landscape& L, const Weather& W, const OutPlan& o,
+             int32_t precision, int32_t item) {
+    Job j;
+    memset(&j, 0, sizeof j);
+    j.cells = L.cells;
+    j.burnable = L.burnable;
+    j.land = L.land;
+    j.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
+    j.table64 = W.t64;
+    j.rows = L.rows;
+    j.cols = L.cols;
+    j.d_orth = L.cell_m;
+    j.d_diag = axis_diag(L.cell_m);
+    j.n_scen = W.n_scen;
+    j.n_wp = W.n_periods;
+    j.period_min = W.period_min;
+    j.n_periods = p.n_periods;
+    j.T = p.n_periods * W.period_min;
+    j.reps = p.reps;
+    j.rep_offset = p.rep_offset;
+    j.item_base = item;
+    j.rounding = p.rounding;
+    j.ign_mode = p.ignition_mode;
+    j.ign_cell = p.ignition_cell;
+    j.scen_mode = p.scenario_mode;
+    j.scen_fixed = p.scenario;
+    j.ign_period = p.ignition_period;
+    j.ign_cdf = p.ignition_mode == 3 ? L.ign_cdf : nullptr;
+    j.n_seeds = 0;
+    if (p.ignition_mode == 4) {
+        // the list by period; entries of one period keep their order
+        int32_t ord[kMaxIgnitions];
+        for (int32_t k = 0; k < p.n_ignitions; ++k) ord[k] = k;
+        std::stable_sort(ord, ord + p.n_ignitions, [&](int32_t a, int32_t b) {
+            return p.ignition_list[2 * a + 1] < p.ignition_list[2 * b + 1];
+        });
+        for (int32_t k = 0; k < p.n_ignitions; ++k)
+            j.seeds[k] = make_int2(p.ignition_list[2 * ord[k]], p.ignition_list[2 * ord[k] + 1]);
+        j.n_seeds = p.n_ignitions;
+        j.ign_period = j.seeds[0].y;
+    }
+    j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
+    j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
+    j.burnout = p.burnout_ros;
+    j.sigma = p.ros_sigma;
+    j.threshold = p.ros_threshold;
+    j.seed = p.seed;
+    j.scar = o.scar;
+    j.arr_period = o.arr_period;
+    j.arr_minute = o.arr_minute;
+    j.count = o.count;
+    j.burned = o.burned;
+    j.ign_out = o.ign;
+    j.scen_out = o.scen;
+    return j;
+}
+
 // One fused launch over all requests of one precision.  Relaunches with a
 // larger list capacity if any work list overflowed.
 c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const std::vector<c2f_sim_params>& P,
@@ -782,59 +843,7 @@ c2f_status run_group(c2f_ctx* ctx, Exec& ex, const std::vector<int>& idx, const 
             const Landscape& L = *Ls[k];
             const Weather& W = *Ws[k];
             const OutPlan& o = plans[k];
-            Job j;
-            memset(&j, 0, sizeof j);
-            j.cells = L.cells;
-            j.burnable = L.burnable;
-            j.land = L.land;
-            j.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
-            j.table64 = W.t64;
-            j.rows = L.rows;
-            j.cols = L.cols;
-            j.d_orth = L.cell_m;
-            j.d_diag = axis_diag(L.cell_m);
-            j.n_scen = W.n_scen;
-            j.n_wp = W.n_periods;
-            j.period_min = W.period_min;
-            j.n_periods = p.n_periods;
-            j.T = p.n_periods * W.period_min;
-            j.reps = p.reps;
-            j.rep_offset = p.rep_offset;
-            j.item_base = item;
-            j.rounding = p.rounding;
-            j.ign_mode = p.ignition_mode;
-            j.ign_cell = p.ignition_cell;
-            j.scen_mode = p.scenario_mode;
-            j.scen_fixed = p.scenario;
-            j.ign_period = p.ignition_period;
-            j.ign_cdf = p.ignition_mode == 3 ? L.ign_cdf : nullptr;
-            j.n_seeds = 0;
-            if (p.ignition_mode == 4) {
-                // the list by period; entries of one period keep their order
-                int32_t ord[kMaxIgnitions];
-                for (int32_t k = 0; k < p.n_ignitions; ++k) ord[k] = k;
-                std::stable_sort(ord, ord + p.n_ignitions, [&](int32_t a, int32_t b) {
-                    return p.ignition_list[2 * a + 1] < p.ignition_list[2 * b + 1];
-                });
-                for (int32_t k = 0; k < p.n_ignitions; ++k)
-                    j.seeds[k] = make_int2(p.ignition_list[2 * ord[k]], p.ignition_list[2 * ord[k] + 1]);
-                j.n_seeds = p.n_ignitions;
-                j.ign_period = j.seeds[0].y;
-            }
-            j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
-            j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
-            j.burnout = p.burnout_ros;
-            j.sigma = p.ros_sigma;
-            j.threshold = p.ros_threshold;
-            j.seed = p.seed;
-            j.scar = o.scar;
-            j.arr_period = o.arr_period;
-            j.arr_minute = o.arr_minute;
-            j.count = o.count;
-            j.burned = o.burned;
-            j.ign_out = o.ign;
-            j.scen_out = o.scen;
-            ex.h_jobs[q] = j;
+            ex.h_jobs[q] = make_job(p, L, W, o, precision, item);
             item += p.reps;
         }
         HIP_TRY(ctx, hipMemcpyAsync(ex.d_jobs, ex.h_jobs, idx.size() * sizeof(Job), hipMemcpyHostToDevice,
@@ -1310,6 +1319,28 @@ c2f_status start_lanes(c2f_ctx* ctx) {
 
 // ===================================================================== ABI
 
+// Launch sizes of a no-allocation run: everything inside the device scratch.
+namespace {
+constexpr int64_t kNoallocFirstCap = 4096;   // list entries per slot before any overflow
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void record_stats(Exec& ex, const RunCounters& rc, int32_t block, int32_t grid, int64_t cap, float ms) {
+    ex.last.kernel_ms += ms;
+    ex.last.entries += (int64_t)rc.c[kCntEntries];
+    ex.last.rate_evals += (int64_t)rc.c[kCntEvals];
+    ex.last.candidates += (int64_t)rc.c[kCntCandidates];
+    ex.last.improvements += (int64_t)rc.c[kCntImprovements];
+    ex.last.ignitions += (int64_t)rc.c[kCntIgnitions];
+    ex.last.rounds += (int64_t)rc.c[kCntRounds];
+    ex.last.continuations += (int64_t)rc.c[kCntConts];
+    ex.last.block_threads = block;
+    ex.last.grid_blocks = grid;
+    ex.last.list_capacity = cap;
+    ex.last.rep_order = 0;
+}
+}  // namespace
+
 extern "C" {
 
 c2f_status c2f_create(int32_t device, uint64_t hbm_budget_bytes, c2f_ctx** out) {
@@ -1333,6 +1364,12 @@ c2f_status c2f_create(int32_t device, uint64_t hbm_budget_bytes, c2f_ctx** out) 
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C2F_EDEVICE;
     ctx->admit_limit = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+    // the no-allocation scratch: its address on this device, resolved once
+    // per device with the device current
+    if (scratch_resolve(device, &ctx->scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        return C2F_EDEVICE;
+    }
     if (exec_init(ctx.get(), ctx->main, false) != C2F_OK) {
         exec_release(ctx.get(), ctx->main);
         return C2F_EDEVICE;
@@ -1818,6 +1855,81 @@ c2f_status c2f_simulate_batch(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
     return simulate_impl(ctx, n_jobs, params, out, true);
+}
+
+c2f_status c2f_simulate_noalloc(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
+    if (!out) return fail(ctx, C2F_EINVAL, "out is NULL");
+    if (!out->on_device) return fail(ctx, C2F_EINVAL, "c2f_simulate_noalloc needs device outputs (on_device = 1)");
+    if (!ctx->scratch) return fail(ctx, C2F_EDEVICE, "no device scratch on device %d", ctx->device);
+    Landscape* L;
+    Weather* W;
+    c2f_status st = check_params(ctx, params, &L, &W);
+    if (st != C2F_OK) return st;
+    const c2f_sim_params& p = *params;
+    const int64_t cells = L->ncells();
+    OutPlan o;
+    o.user = *out;
+    o.scar = out->scar;
+    o.arr_period = out->arrival_period;
+    o.arr_minute = out->arrival_minute;
+    o.count = out->burn_count;
+    o.burned = out->burned_cells;
+    o.ign = out->ignition_cell;
+    o.scen = out->scenario;
+    LaunchPlan lp = plan_launch(ctx, cells, p.reps, p.precision, 0);
+    // Layout: run counters | job record | tags[slots] | planes[slots] | lists[slots]
+    const size_t head = align256(sizeof(RunCounters)) + align256(sizeof(Job));
+    const size_t plane_b = align256((size_t)cells * 4);
+    const int64_t cap_max = std::min<int64_t>(std::max<int64_t>(4 * cells, 1 << 12) * 8, (int64_t)1 << 30);
+    int64_t cap = std::min<int64_t>(std::min(lp.cap, kNoallocFirstCap), cap_max);
+    Exec& ex = ctx->main;
+    std::lock_guard<std::mutex> slk(scratch_lock(ctx->device));
+    uint8_t* const base = (uint8_t*)ctx->scratch;
+    RunCounters* const rc = (RunCounters*)base;
+    Job* const job = (Job*)(base + align256(sizeof(RunCounters)));
+    memset(&ex.last, 0, sizeof ex.last);
+    for (;;) {
+        const size_t per_slot = plane_b + (size_t)cap * kSlotListBytesPerEntry + 4;
+        const size_t avail = kScratchBytes - head - 256;   // 256: the tag array's rounding
+        const int64_t fit = (int64_t)(avail / per_slot);
+        if (fit < 1)
+            return fail(ctx, C2F_EINVAL,
+                        "request needs %zu bytes of device scratch for one work slot (%lld cells, %lld list "
+                        "entries); c2f_simulate_noalloc has %zu bytes (use c2f_simulate)",
+                        head + 256 + per_slot, (long long)cells, (long long)cap, kScratchBytes);
+        const int32_t slots = (int32_t)std::min<int64_t>(lp.grid, fit);
+        uint32_t* const tags = (uint32_t*)(base + head);
+        uint32_t* const planes = (uint32_t*)(base + head + align256((size_t)slots * 4));
+        uint8_t* const lists = (uint8_t*)planes + (size_t)slots * plane_b;
+        if (lists + (size_t)slots * (size_t)cap * kSlotListBytesPerEntry > base + kScratchBytes)
+            return fail(ctx, C2F_EINVAL, "scratch layout exceeds the scratch");   // cannot happen
+        const Slots sl{planes, (int64_t)(plane_b / 4), lists, cap, cap, tags, nullptr, nullptr};
+        // tags 0: every slot refills its plane before its first replication,
+        // so nothing a previous call left in the scratch is read
+        HIP_TRY(ctx, launch_fill_u32((uint32_t*)rc, sizeof(RunCounters) / 4, 0u, ex.stream));
+        HIP_TRY(ctx, launch_fill_u32(tags, (size_t)slots, 0u, ex.stream));
+        if (o.count) HIP_TRY(ctx, launch_fill_u32(o.count, (size_t)cells, 0u, ex.stream));
+        HIP_TRY(ctx, launch_store_job(make_job(p, *L, *W, o, p.precision, 0), job, ex.stream));
+        HIP_TRY(ctx, hipEventRecord(ex.ev0, ex.stream));
+        HIP_TRY(ctx, launch_propagate(p.precision, lp.block, slots, job, 1, p.reps, sl, rc, ex.stream));
+        HIP_TRY(ctx, hipEventRecord(ex.ev1, ex.stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ex.rc_host, rc, sizeof(RunCounters), hipMemcpyDeviceToHost, ex.stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ex.ev0, ex.ev1));
+        if (ex.rc_host->overflow == 0) {
+            record_stats(ex, *ex.rc_host, lp.block, slots, cap, ms);
+            return C2F_OK;
+        }
+        ++ex.last.relaunches;
+        if (cap >= cap_max)
+            return fail(ctx, C2F_ECAPACITY, "work lists overflow at capacity %lld", (long long)cap);
+        cap = std::min(cap_max, cap * 4);
+    }
 }
 
 c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, int32_t scenario, int32_t period,

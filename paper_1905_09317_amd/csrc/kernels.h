@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "types.h"
 
 namespace c2f {
@@ -52,5 +54,15 @@ hipError_t launch_order(int precision, const Job* jobs, int n_jobs, int total_it
 // total <= 65535; nothing is written if the launch overflowed.
 hipError_t launch_dense_outputs(const Job* jobs, int n_jobs, int total, int n_slots, int64_t max_cells,
                                 const Slots& slots, const RunCounters* rc, hipStream_t s);
+
+// No-allocation scratch (noalloc.hip): kScratchBytes of device memory per
+// device, held for the life of the process.  scratch_resolve gives the
+// device address of `device`'s copy (resolved once, with that device
+// current); scratch_lock serialises its users within the process.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+hipError_t scratch_resolve(int device, void** out);
+std::mutex& scratch_lock(int device);
+// *dst = j, ordered on s (the job record of a launch, without host staging).
+hipError_t launch_store_job(const Job& j, Job* dst, hipStream_t s);
 
 }  // namespace c2f
