@@ -7,10 +7,17 @@ over every period, and the reduction into burn counts and per-rep outputs,
 all in the HIP library (one hipGraph launch of the fused kernel).
 
 Prints one JSON line.  value = cell-updates/s = reps x cells x periods per
-second (whole job).  The roofline object describes the propagation kernel:
-algorithmic bytes per launch (per-unit byte figures x the kernel's own
-event counters) over its HIP-event duration.  cpu_baseline times the FP64
-reference oracle on the same workload on the host (one core).
+second (whole job).  The default workload is the largest single-GPU one:
+an 8192 x 8192 landscape, 64 replications, 72 hourly periods, FP64 rates.
+The roofline object describes the propagation kernel: algorithmic bytes per
+launch over its HIP-event duration, where the bytes are per-unit figures
+times the work units of the minute-stepping method (burning-cell-periods,
+axis reach events, ignitions) counted from the run's final arrival minutes
+by the library (c2f_count_work), not the kernel's own work counters (those
+are reported beside them as a redundancy ratio).  roofline.step adds the
+burn-count array and the requested outputs over the whole step.
+cpu_baseline times the FP64 reference oracle on a bounded sample of the
+same workload on the host.
 """
 from __future__ import annotations
 
@@ -24,15 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Per-unit algorithmic bytes of the propagation kernel:
-#   rate evaluation (a burning cell in a period): 5 B landscape (fuel + slope)
-#     + 16 B work-list entry read + 16 B entry write           = 37 B
-#   arrival candidate offered to a neighbour: 1 B fuel + 8 B label RMW = 9 B
-#   ignition: 16 B list append + 8 B burn-count RMW              = 24 B
-#   per cell per rep of dense outputs: 4 B label read + 1 B scar + 4 B period,
-#     counted only when the propagation kernel writes them itself (a launch
-#     where every replication keeps its slot leaves them to a grid-wide kernel)
-# The burn-count initialisation (4 B per cell) is a separate fill kernel.
-B_EVAL, B_CAND, B_IGN, B_DENSE = 37, 9, 24, 9
+#   burning-cell-period: 5 B landscape (fuel + slope) + 16 B work-list entry
+#     read + 16 B entry write                                     = 37 B
+#   axis reach event: 1 B neighbour fuel + 8 B arrival label RMW   = 9 B
+#   ignition: 16 B list append + 8 B burn-count RMW                 = 24 B
+# A step adds 4 B per cell of burn counts and the requested per-rep outputs
+# (1 B scar, 4 B arrival period, 8 B burned cells).
+B_EVAL, B_CAND, B_IGN = 37, 9, 24
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the propagation kernel measured with rocprofv3
@@ -75,6 +80,19 @@ def make_workload(name: str):
     if name == "tiny":
         return inputs.tiny_c2()
     raise SystemExit(f"unknown workload {name}")
+
+
+def work_units(sim, req) -> dict:
+    """The method's work units of the request (c2f_count_work), from the final
+    arrival minutes of one more, untimed run of the same request."""
+    import dataclasses
+
+    import torch
+    o = sim.simulate(dataclasses.replace(req, outputs=("arrival_minute",), device_out=True))
+    units = sim.count_work(req, o["arrival_minute"])
+    del o
+    torch.cuda.empty_cache()
+    return units
 
 
 def dense_outputs(w) -> tuple:
@@ -312,7 +330,12 @@ def treatment_bench(args) -> None:
     torch.cuda.synchronize()
     ms_alone = (time.perf_counter() - t0) * 1e3
     same = all(torch.equal(a["burn_count"], b["burn_count"]) for a, b in zip(alone, outs))
-    alg_bytes = B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"]
+    units = {"burning_cell_periods": 0, "axis_reaches": 0, "ignitions": 0}
+    for r in reqs:
+        for k, v in work_units(sim, r).items():
+            units[k] += v
+    alg_bytes = (B_EVAL * units["burning_cell_periods"] + B_CAND * units["axis_reaches"]
+                 + B_IGN * units["ignitions"])
     kernel_ms = sum(kms) / len(kms)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     cell_updates = n_plans * reps * w.rows * w.cols * w.n_periods
@@ -338,7 +361,7 @@ def treatment_bench(args) -> None:
         "mean_burn_probability": p_burn,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "c2f::propagate_kernel",
-                     "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes},
+                     "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes, "units": units},
     }
     sim.close()
     if not args.no_cpu_baseline:
@@ -438,7 +461,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single",
+    ap.add_argument("--workload", default="large",
                     choices=["single", "single64", "batched", "large", "tiny", "served", "treatments",
                              "scars"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -527,16 +550,21 @@ def main():
 
     st = stats[-1]
     n = w.rows * w.cols
-    deferred = w.reps <= st["grid_blocks"]
-    dense = w.reps * n * B_DENSE if ("scar" in dense_outputs(w) and not deferred) else 0
-    alg_bytes = B_EVAL * st["rate_evals"] + B_CAND * st["candidates"] + B_IGN * st["ignitions"] + dense
+    kernel_ms = sum(kms) / len(kms)
+    burned = int(out["burned_cells"].sum().item())
+    print("[bench] counting the work units", file=sys.stderr, flush=True)
+    units = work_units(sim, req)
+    alg_bytes = (B_EVAL * units["burning_cell_periods"] + B_CAND * units["axis_reaches"]
+                 + B_IGN * units["ignitions"])
+    per_rep_out = {"scar": 1, "arrival_period": 4, "arrival_minute": 4}
+    step_bytes = (alg_bytes + 4 * n + 8 * w.reps
+                  + w.reps * n * sum(per_rep_out.get(k, 0) for k in dense_outputs(w)))
     traffic = None
     # counters were taken at the workload's own precision
     if w.name in TRAFFIC and TRAFFIC[w.name][0] == kernel_digest() and w.precision == default_precision:
         traffic = TRAFFIC[w.name][1]
-    kernel_ms = sum(kms) / len(kms)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-    burned = int(out["burned_cells"].sum().item())
+    step_achieved = step_bytes / (ms / 1e3) / 1e9
 
     line = {
         "metric": "cell-updates/s (reps x cells x periods)",
@@ -568,7 +596,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "c2f::propagate_kernel", "kernel_ms": kernel_ms,
                      "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_per_cell_update": alg_bytes / (w.reps * w.rows * w.cols * w.n_periods)},
+                     "alg_bytes_per_cell_update": alg_bytes / (w.reps * w.rows * w.cols * w.n_periods),
+                     "units": units,
+                     "step": {"alg_bytes": step_bytes, "ms": ms, "achieved": step_achieved,
+                              "frac": step_achieved / HBM_PEAK_GBS},
+                     "redundancy": {
+                         "rate_evals_per_burning_cell_period":
+                             st["rate_evals"] / max(1, units["burning_cell_periods"]),
+                         "candidates_per_axis_reach": st["candidates"] / max(1, units["axis_reaches"])}},
     }
     n_single = args.per_launch if args.per_launch >= 0 else (64 if w.reps > 1 else 0)
     if n_single > 0 and w.reps > 1:

@@ -262,6 +262,20 @@ c2f_status c2f_simulate_batch(c2f_ctx* ctx, int32_t n_jobs, const c2f_sim_params
  * process, and calls that overlapped on one device would race. */
 c2f_status c2f_simulate_noalloc(c2f_ctx* ctx, const c2f_sim_params* params, const c2f_outputs* out);
 
+/* Work counts of a finished request, for measuring the algorithmic bytes of
+ * the sending stage (Section 3.8, App. A; Algorithm 1 Step 2).  From the
+ * request's final arrival minutes (arrival_minute output of c2f_simulate
+ * with the same params: device pointer, int32 [reps][rows*cols], -1 =
+ * unburned) it writes counts[0] = burning-cell-periods, the (replication,
+ * cell, period) triples whose rates the cell takes while some axis still
+ * leads to a neighbour that has not ignited; counts[1] = axis reach events,
+ * progress along an axis reaching the neighbour's centre before it ignites;
+ * counts[2] = ignitions (burned cells).  These are the minute-stepping
+ * loop's own units, independent of how the simulation ordered its work.
+ * Synchronous on the context's stream; counts is a host array of 3. */
+c2f_status c2f_count_work(c2f_ctx* ctx, const c2f_sim_params* params, const int32_t* arrival_minute,
+                          int64_t* counts);
+
 /* Parity/debug: the per-cell FBP field of one (scenario, period, rep) on the
  * landscape, exactly as the simulation computes it.  Host outputs, any may
  * be NULL, each [rows*cols] (q8 and x8: [rows*cols][8]):

@@ -161,7 +161,9 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
     pairs [k, 2] lit as the clock reaches their periods (ignition_mode 4,
     set by passing them).
     Returns scar/arrival_period/arrival_minute [reps, rows*cols] (if wanted),
-    burn_count [rows*cols], burned_cells/ignition_cell/scenario [reps], stats [3].
+    burn_count [rows*cols], burned_cells/ignition_cell/scenario [reps], stats [5]
+    (ignitions, burning-cell-minutes, rate evaluations, burning-cell-periods,
+    axis reach events).
     """
     f, e, w = _land(fuel, elev, weather)
     rows, cols = f.shape
@@ -175,7 +177,7 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
     res["burned_cells"] = np.zeros(reps, np.int64)
     res["ignition_cell"] = np.zeros(reps, np.int32)
     res["scenario"] = np.zeros(reps, np.int32)
-    res["stats"] = np.zeros(3, np.int64)
+    res["stats"] = np.zeros(5, np.int64)
     n_ov, ok, oq = 0, None, None
     if overrides is not None and len(overrides[0]) > 0:
         ok = np.ascontiguousarray(overrides[0], dtype=np.int32).reshape(-1, 3)

@@ -618,7 +618,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
     size_t cap = 1024;
     burning_t* burn = (burning_t*)malloc(sizeof(burning_t) * cap);
     if (burn_count) memset(burn_count, 0, sizeof(uint32_t) * (size_t)n);
-    int64_t st_ign = 0, st_bcm = 0, st_fbp = 0;
+    int64_t st_ign = 0, st_bcm = 0, st_fbp = 0, st_bp = 0, st_ax = 0;
 
     for (int32_t lr = 0; lr < reps; ++lr) {
         const int32_t rep = rep_offset + lr;
@@ -706,6 +706,15 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
             for (size_t bi = 0; bi < nb; ++bi) {
                 burning_t* b = &burn[bi];
                 if (b->qperiod != p) {
+                    /* a burning-cell-period: the cell's rates for p are taken
+                     * while some axis still leads to an available neighbour */
+                    for (int k = 0; k < 8; ++k) {
+                        int j = neighbour(&L, b->cell, k);
+                        if (j >= 0 && fuel[j] != 0 && arrival[j] == INF_T && b->prog[k] < L.d[k]) {
+                            ++st_bp;
+                            break;
+                        }
+                    }
                     const int32_t* oq = ov.n ? override_find(&ov, rep, p, b->cell) : NULL;
                     if (oq) {
                         for (int k = 0; k < 8; ++k) b->q[k] = oq[k];
@@ -733,6 +742,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                     if (j < 0 || fuel[j] == 0 || arrival[j] != INF_T || b->prog[k] >= L.d[k]) continue;
                     b->prog[k] += b->q[k];
                     if (b->prog[k] >= L.d[k]) {
+                        ++st_ax;   /* an axis reach event: the neighbour's centre is reached */
                         b->prog[k] = L.d[k];
                         if (!reached[j]) {
                             reached[j] = 1;
@@ -807,6 +817,8 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
         stats[0] = st_ign;
         stats[1] = st_bcm;
         stats[2] = st_fbp;
+        stats[3] = st_bp;
+        stats[4] = st_ax;
     }
     free(seeds);
     free(burn);

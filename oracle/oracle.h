@@ -68,7 +68,11 @@ int oracle_eval_ros_cells(int32_t rows, int32_t cols, int32_t cell_m, const uint
  * overwritten; burned_cells, ignition_cell, scenario_out are [reps].
  * n_override entries (rep, period, cell) -> q[8] replace computed integer
  * axis rates (data only; used to replay another implementation's rounding).
- * stats (may be NULL) receives [ignitions, burning-cell-minutes, fbp evals]. */
+ * stats (may be NULL) receives [ignitions, burning-cell-minutes, fbp evals,
+ * burning-cell-periods, axis reach events]: a burning-cell-period is a
+ * (replication, cell, period) whose rates the cell takes while burning
+ * with at least one axis still leading to an available neighbour; an axis
+ * reach event is progress along an axis reaching the neighbour's centre. */
 int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
                     const int16_t* elev, double pc_pct, double curing_pct,
                     int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,

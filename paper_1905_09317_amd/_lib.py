@@ -87,6 +87,7 @@ def load() -> ctypes.CDLL:
         "c2f_simulate": ([P, pp(SimParams), pp(Outputs)], i32),
         "c2f_simulate_batch": ([P, i32, pp(SimParams), pp(Outputs)], i32),
         "c2f_simulate_noalloc": ([P, pp(SimParams), pp(Outputs)], i32),
+        "c2f_count_work": ([P, pp(SimParams), P, P], i32),
         "c2f_eval_ros": ([P, i32, i32, i32, i32, i32, u64, f32, i32, i32, P, P, P, P, P, P, P], i32),
         "c2f_fbp_coefficients": ([i32, P], i32),
         "c2f_set_tuning": ([P, i32, i64], i32),
@@ -114,7 +115,7 @@ def load() -> ctypes.CDLL:
 
 DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2f_load_landscape",
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
-            "c2f_simulate_batch", "c2f_simulate_noalloc", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
+            "c2f_simulate_batch", "c2f_simulate_noalloc", "c2f_count_work", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
             "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
             "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_rep_order",
             "c2f_set_ignition_map", "c2f_derive_landscape", "c2f_compare_scars",

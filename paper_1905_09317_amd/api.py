@@ -276,6 +276,23 @@ class Simulator:
         self._check(self._L.c2f_simulate_noalloc(self._ctx, ctypes.byref(p), ctypes.byref(o)))
         return res
 
+    def count_work(self, req: Request, arrival_minute) -> dict:
+        """Work counts of a finished request from its arrival minutes (a device
+        tensor [reps, rows*cols] int32, as simulate returns with
+        device_out=True): burning-cell-periods, axis reach events, ignitions."""
+        import torch
+        a = arrival_minute
+        lm = self._lands[req.landscape]
+        if (not isinstance(a, torch.Tensor) or not a.is_cuda or a.dtype != torch.int32
+                or not a.is_contiguous() or a.numel() != req.reps * lm.rows * lm.cols):
+            raise ValueError("arrival_minute must be a contiguous int32 device tensor [reps, cells]")
+        self.set_stream(torch.cuda.current_stream(self._device))
+        out = np.zeros(3, np.int64)
+        p = req.params()
+        self._check(self._L.c2f_count_work(self._ctx, ctypes.byref(p), ctypes.c_void_p(a.data_ptr()),
+                                           out.ctypes.data_as(ctypes.c_void_p)))
+        return {"burning_cell_periods": int(out[0]), "axis_reaches": int(out[1]), "ignitions": int(out[2])}
+
     def simulate_batch(self, reqs: list[Request]) -> list[dict]:
         """Run several requests (any landscapes/weather) in one fused launch."""
         if any(r.device_out for r in reqs):

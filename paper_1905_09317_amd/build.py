@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libc2f.so")
-SOURCES = ["prep.hip", "propagate.hip", "order.hip", "metrics.hip", "noalloc.hip", "capi.cpp"]
+SOURCES = ["prep.hip", "propagate.hip", "order.hip", "metrics.hip", "noalloc.hip", "account.hip", "capi.cpp"]
 HEADERS = ["device.h", "fuel_table.h", "kernels.h", "ln64.h", "types.h"]
 
 HIPCC_FLAGS = [

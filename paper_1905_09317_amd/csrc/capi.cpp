@@ -170,6 +170,7 @@ struct c2f_ctx {
     int n_cu = 0;
     std::chrono::steady_clock::time_point t0;
     void* scratch = nullptr;    // device address of the no-allocation scratch on `device`
+    void* acct = nullptr;       // work counts: 3 counters and a job record (allocated on first use)
 
     std::mutex errmu;
     std::string err;
@@ -1392,6 +1393,7 @@ void c2f_destroy(c2f_ctx* ctx) {
     ctx->lanes.clear();
     exec_release(ctx, ctx->main);
     if (ctx->metric_buf) (void)hipFree(ctx->metric_buf);
+    if (ctx->acct) (void)hipFree(ctx->acct);
     for (auto& kv : ctx->lands) {
         (void)hipFree(kv.second.fuel);
         (void)hipFree(kv.second.cells);
@@ -1930,6 +1932,37 @@ c2f_status c2f_simulate_noalloc(c2f_ctx* ctx, const c2f_sim_params* params, cons
             return fail(ctx, C2F_ECAPACITY, "work lists overflow at capacity %lld", (long long)cap);
         cap = std::min(cap_max, cap * 4);
     }
+}
+
+c2f_status c2f_count_work(c2f_ctx* ctx, const c2f_sim_params* params, const int32_t* arrival_minute,
+                          int64_t* counts) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
+    if (!arrival_minute || !counts) return fail(ctx, C2F_EINVAL, "arrival_minute and counts are required");
+    Landscape* L;
+    Weather* W;
+    c2f_status st = check_params(ctx, params, &L, &W);
+    if (st != C2F_OK) return st;
+    const size_t job_off = 256;
+    if (!ctx->acct) {
+        st = dev_alloc(ctx, &ctx->acct, job_off + sizeof(Job));
+        if (st != C2F_OK) return st;
+    }
+    Exec& ex = ctx->main;
+    unsigned long long* cnt = (unsigned long long*)ctx->acct;
+    Job* job = (Job*)((char*)ctx->acct + job_off);
+    const OutPlan none;
+    HIP_TRY(ctx, launch_fill_u32((uint32_t*)cnt, 6, 0u, ex.stream));
+    HIP_TRY(ctx, launch_store_job(make_job(*params, *L, *W, none, params->precision, 0), job, ex.stream));
+    HIP_TRY(ctx, launch_work_counts(params->precision, job, L->ncells() * (int64_t)params->reps, arrival_minute,
+                                    cnt, ex.stream));
+    unsigned long long h[3];
+    HIP_TRY(ctx, hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, ex.stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
+    for (int k = 0; k < 3; ++k) counts[k] = (int64_t)h[k];
+    return C2F_OK;
 }
 
 c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, int32_t scenario, int32_t period,

@@ -55,6 +55,13 @@ hipError_t launch_order(int precision, const Job* jobs, int n_jobs, int total_it
 hipError_t launch_dense_outputs(const Job* jobs, int n_jobs, int total, int n_slots, int64_t max_cells,
                                 const Slots& slots, const RunCounters* rc, hipStream_t s);
 
+// Work counts of a finished request (account.hip): out[0..2] +=
+// burning-cell-periods, axis reach events, ignitions, from the final arrival
+// minutes [reps][rows*cols] (-1 unburned) of the request described by *job
+// (device); total_cells = reps * rows * cols.
+hipError_t launch_work_counts(int precision, const Job* job, int64_t total_cells, const int32_t* arrival,
+                              unsigned long long* out, hipStream_t s);
+
 // No-allocation scratch (noalloc.hip): kScratchBytes of device memory per
 // device, held for the life of the process.  scratch_resolve gives the
 // device address of `device`'s copy (resolved once, with that device
