@@ -42,20 +42,24 @@ def _load():
         L.oracle_fuel_coefficients.argtypes = [i32, P]
         L.oracle_fuel_coefficients.restype = ctypes.c_int
         L.oracle_fbp_point.argtypes = [i32, f64, f64, f64, f64, f64, f64, f64, f64, P]
+        L.oracle_fbp_point_ext.argtypes = [i32, f64, f64, f64, f64, f64, f64, f64, f64, f64, f64, P]
+        L.oracle_crown_coefficients.argtypes = [i32, P]
+        L.oracle_crown_coefficients.restype = ctypes.c_int
         L.oracle_axis_ros.argtypes = [f64, f64, f64, f64, P]
         L.oracle_axis_ros.restype = None
         L.oracle_eval_ros.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, P, i32, i32, i32,
                                       u64, f64, i32, P, P, P, P, P, P, P, P]
-        L.oracle_eval_ros_cells.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, P, i32, i32,
-                                            i32, u64, f64, i32, i64, P, P, P, P, P, P, P, P, P]
+        L.oracle_eval_ros_cells.argtypes = [i32, i32, i32, P, P, f64, f64, f64, f64, i32, i32, P, i32,
+                                            i32, i32, u64, f64, i32, i64, P, P, P, P, P, P, P, P, P, P,
+                                            P]
         L.oracle_simulate.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
                                       i32, i32, i32, u64, f64, f64, i32, i32, i32, i32, i32,
                                       i32, P, P, P, P, P, P, P, P, P, P]
-        L.oracle_simulate_ext.argtypes = [i32, i32, i32, P, P, f64, f64, i32, i32, i32, P,
+        L.oracle_simulate_ext.argtypes = [i32, i32, i32, P, P, f64, f64, f64, f64, i32, i32, i32, P,
                                           i32, i32, i32, u64, f64, f64, i32, i32, i32, P, i32, i32,
-                                          f64, i32, P, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
+                                          f64, f64, i32, P, i32, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.oracle_scar_metrics.argtypes = [i64, i32, i32, P, P, P, P, P]
-        for fn in ("oracle_horn", "oracle_fbp_point", "oracle_eval_ros", "oracle_eval_ros_cells",
+        for fn in ("oracle_horn", "oracle_fbp_point", "oracle_fbp_point_ext", "oracle_eval_ros", "oracle_eval_ros_cells",
                    "oracle_simulate", "oracle_simulate_ext", "oracle_scar_metrics"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -81,6 +85,14 @@ def fuel_coefficients(fuel: int) -> np.ndarray:
     return out
 
 
+def crown_coefficients(fuel: int) -> np.ndarray:
+    """Crown base height (m) and crown fuel load (kg/m^2) of a fuel code."""
+    out = np.zeros(2, np.float64)
+    if _load().oracle_crown_coefficients(int(fuel), _ptr(out)) != 0:
+        raise ValueError("bad fuel code")
+    return out
+
+
 def horn(elev: np.ndarray):
     e = np.ascontiguousarray(elev, dtype=np.int16)
     r, c = e.shape
@@ -91,15 +103,17 @@ def horn(elev: np.ndarray):
     return gx, gn
 
 
-FBP_FIELDS = ("hros", "bros", "fros", "lb", "raz", "isi", "wsv", "be", "rsi", "wse")
+FBP_FIELDS = ("hros", "bros", "fros", "lb", "raz", "isi", "wsv", "be", "rsi", "wse", "sfc", "cfb",
+              "tfc", "hfi")
 
 
 def fbp_point(fuel: int, ffmc: float, bui: float, ws: float, wd: float, slope_pct: float = 0.0,
-              upslope_az: float = 0.0, pc: float = 50.0, curing: float = 80.0) -> dict:
-    out = np.zeros(10, np.float64)
-    rc = _load().oracle_fbp_point(int(fuel), float(ffmc), float(bui), float(ws), float(wd),
-                                  float(slope_pct), float(upslope_az), float(pc), float(curing),
-                                  _ptr(out))
+              upslope_az: float = 0.0, pc: float = 50.0, curing: float = 80.0, fmc: float = 97.0,
+              pdf: float = 50.0) -> dict:
+    out = np.zeros(14, np.float64)
+    rc = _load().oracle_fbp_point_ext(int(fuel), float(ffmc), float(bui), float(ws), float(wd),
+                                      float(slope_pct), float(upslope_az), float(pc), float(curing),
+                                      float(fmc), float(pdf), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_fbp_point: bad input")
     return dict(zip(FBP_FIELDS, out.tolist()))
@@ -123,24 +137,26 @@ def _land(fuel, elev, weather):
 
 
 def eval_ros(fuel, elev, weather, *, cell_m=100, scenario=0, period=0, rep=0, seed=0, sigma=0.0,
-             rounding=0, pc=50.0, curing=80.0, cells=None) -> dict:
+             rounding=0, pc=50.0, curing=80.0, fmc=97.0, pdf=50.0, cells=None) -> dict:
     """Per-cell rate field; with `cells` (grid indices) only those cells,
     outputs indexed by position in `cells`."""
     f, e, w = _land(fuel, elev, weather)
     rows, cols = f.shape
     sel = None if cells is None else np.ascontiguousarray(cells, dtype=np.int32)
     n = rows * cols if sel is None else sel.size
-    out = {k: np.zeros(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz")}
+    out = {k: np.zeros(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz", "cfb", "hfi")}
     out["x8"] = np.zeros((n, 8), np.float64)
     out["xu8"] = np.zeros((n, 8), np.float64)
     out["q8"] = np.zeros((n, 8), np.int32)
     rc = _load().oracle_eval_ros_cells(rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc),
-                                       float(curing), w.shape[0], w.shape[1], _ptr(w), int(scenario),
+                                       float(curing), float(fmc), float(pdf), w.shape[0], w.shape[1],
+                                       _ptr(w), int(scenario),
                                        int(period), int(rep), int(seed) & (2**64 - 1), float(sigma),
                                        int(rounding), -1 if sel is None else int(sel.size),
                                        _ptr(sel), _ptr(out["hros"]), _ptr(out["bros"]),
                                        _ptr(out["fros"]), _ptr(out["lb"]), _ptr(out["raz"]),
-                                       _ptr(out["x8"]), _ptr(out["xu8"]), _ptr(out["q8"]))
+                                       _ptr(out["x8"]), _ptr(out["xu8"]), _ptr(out["q8"]),
+                                       _ptr(out["cfb"]), _ptr(out["hfi"]))
     if rc != 0:
         raise ValueError("oracle_eval_ros: bad input")
     return out
@@ -148,16 +164,17 @@ def eval_ros(fuel, elev, weather, *, cell_m=100, scenario=0, period=0, rep=0, se
 
 def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0, seed=0,
              sigma=0.0, threshold=0.0, rounding=0, ignition_mode=0, ignition_cell=0,
-             scenario_mode=0, scenario=0, period_min=60, pc=50.0, curing=80.0,
+             scenario_mode=0, scenario=0, period_min=60, pc=50.0, curing=80.0, fmc=97.0, pdf=50.0,
              overrides=None, want_rep_outputs=True, ignition_weights=None, ignition_period=0,
-             burn_hours=0, burnout=0.0, ignitions=None) -> dict:
+             burn_hours=0, burnout=0.0, hfi_min=0.0, ignitions=None) -> dict:
     """Run the minute-stepping reference simulation.
 
     overrides: optional (keys int32 [n,3] of (rep, period, cell), q int32 [n,8]).
     ignition_mode 3 draws the ignition from ignition_weights (uint32 per
     cell); ignition_period starts the fire at that period; burn_hours (1..24)
     is the daily burning window (0 = always); burnout (m/min, 0 = off) is the
-    rate below which a burning cell burns out.  ignitions: (cell, period)
+    rate below which a burning cell burns out; hfi_min (kW/m, 0 = off) the
+    head fire intensity below which it does.  ignitions: (cell, period)
     pairs [k, 2] lit as the clock reaches their periods (ignition_mode 4,
     set by passing them).
     Returns scar/arrival_period/arrival_minute [reps, rows*cols] (if wanted),
@@ -193,11 +210,11 @@ def simulate(fuel, elev, weather, *, cell_m=100, n_periods, reps=1, rep_offset=0
         seeds = np.ascontiguousarray(ignitions, dtype=np.int32).reshape(-1, 2)
         ignition_mode = 4
     rc = _load().oracle_simulate_ext(
-        rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc), float(curing), w.shape[0],
-        w.shape[1], int(period_min), _ptr(w), int(reps), int(rep_offset), int(n_periods),
+        rows, cols, int(cell_m), _ptr(f), _ptr(e), float(pc), float(curing), float(fmc), float(pdf),
+        w.shape[0], w.shape[1], int(period_min), _ptr(w), int(reps), int(rep_offset), int(n_periods),
         int(seed) & (2**64 - 1), float(sigma), float(threshold), int(rounding),
         int(ignition_mode), int(ignition_cell), _ptr(iw), int(ignition_period), int(burn_hours),
-        float(burnout), 0 if seeds is None else seeds.shape[0], _ptr(seeds),
+        float(burnout), float(hfi_min), 0 if seeds is None else seeds.shape[0], _ptr(seeds),
         int(scenario_mode), int(scenario), n_ov,
         _ptr(ok), _ptr(oq), _ptr(res.get("scar")), _ptr(res.get("arrival_period")),
         _ptr(res.get("arrival_minute")), _ptr(res["burn_count"]), _ptr(res["burned_cells"]),

@@ -56,27 +56,55 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
 
 /* ------------------------------------------------------ FBP System tables */
 /* Fuel codes: 0 non-fuel, 1-7 C-1..C-7, 8 D-1, 9 M-1, 10 M-2, 11-13 S-1..S-3,
- * 14 O-1a, 15 O-1b.  (Table FBPT shows the code -> FBP type dictionary.) */
+ * 14 O-1a, 15 O-1b, 16 D-2, 17 M-3, 18 M-4.  (Table FBPT shows the code ->
+ * FBP type dictionary idea; the paper counts the FBP System's fuel types in
+ * Section 2.3.) */
 enum { NF = 0, C1 = 1, C2 = 2, C3 = 3, C4 = 4, C5 = 5, C6 = 6, C7 = 7, D1 = 8, M1 = 9, M2 = 10,
-       S1 = 11, S2 = 12, S3 = 13, O1A = 14, O1B = 15 };
+       S1 = 11, S2 = 12, S3 = 13, O1A = 14, O1B = 15, D2 = 16, M3 = 17, M4 = 18, NFUEL = 19 };
 
-/* Rate-of-spread curve RSI = a (1 - exp(-b ISI))^c and BUI effect (q, BUI0). */
-static const double FBP_A[16] = {0, 90, 110, 110, 110, 30, 30, 45, 30, 0, 0, 75, 40, 55, 190, 250};
-static const double FBP_B[16] = {0, 0.0649, 0.0282, 0.0444, 0.0293, 0.0697, 0.0800, 0.0305,
-                                 0.0232, 0, 0, 0.0297, 0.0438, 0.0829, 0.0310, 0.0350};
-static const double FBP_C[16] = {0, 4.5, 1.5, 3.0, 1.5, 4.0, 3.0, 2.0, 1.6, 0, 0, 1.3, 1.7, 3.2, 1.4, 1.7};
-static const double FBP_Q[16] = {0, 0.90, 0.70, 0.75, 0.80, 0.80, 0.80, 0.85, 0.90, 0.80, 0.80,
-                                 0.75, 0.75, 0.75, 1.0, 1.0};
-static const double FBP_BUI0[16] = {0, 72, 64, 62, 66, 56, 62, 106, 32, 50, 50, 38, 63, 31, 1, 1};
+/* Rate-of-spread curve RSI = a (1 - exp(-b ISI))^c and BUI effect (q, BUI0).
+ * M-3 and M-4 carry their dead-fir curves; M-1 and M-2 have none of their
+ * own (they mix C-2 and D-1). */
+static const double FBP_A[NFUEL] = {0, 90, 110, 110, 110, 30, 30, 45, 30, 0, 0, 75, 40, 55, 190, 250,
+                                    6, 120, 100};
+static const double FBP_B[NFUEL] = {0, 0.0649, 0.0282, 0.0444, 0.0293, 0.0697, 0.0800, 0.0305,
+                                    0.0232, 0, 0, 0.0297, 0.0438, 0.0829, 0.0310, 0.0350,
+                                    0.0232, 0.0572, 0.0404};
+static const double FBP_C[NFUEL] = {0, 4.5, 1.5, 3.0, 1.5, 4.0, 3.0, 2.0, 1.6, 0, 0, 1.3, 1.7, 3.2, 1.4, 1.7,
+                                    1.6, 1.4, 1.48};
+static const double FBP_Q[NFUEL] = {0, 0.90, 0.70, 0.75, 0.80, 0.80, 0.80, 0.85, 0.90, 0.80, 0.80,
+                                    0.75, 0.75, 0.75, 1.0, 1.0, 0.9, 0.8, 0.8};
+static const double FBP_BUI0[NFUEL] = {0, 72, 64, 62, 66, 56, 62, 106, 32, 50, 50, 38, 63, 31, 1, 1,
+                                       32, 50, 50};
+/* Crown base height (m) and crown fuel load (kg/m^2) of the fuels that
+ * crown (conifers and mixedwoods); 0 elsewhere. */
+static const double FBP_CBH[NFUEL] = {0, 2, 3, 8, 4, 18, 7, 10, 0, 6, 6, 0, 0, 0, 0, 0, 0, 6, 6};
+static const double FBP_CFL[NFUEL] = {0, 0.75, 0.8, 1.15, 1.2, 1.2, 1.8, 0.5, 0, 0.8, 0.8, 0, 0, 0, 0, 0,
+                                      0, 0.8, 0.8};
+#define GRASS_FUEL_LOAD 0.35 /* kg/m^2, O-1a and O-1b */
 
 int oracle_fuel_coefficients(int32_t fuel, double* out5) {
-    if (fuel < 1 || fuel > 15 || !out5) return -1;
+    if (fuel < 1 || fuel >= NFUEL || !out5) return -1;
     out5[0] = FBP_A[fuel]; out5[1] = FBP_B[fuel]; out5[2] = FBP_C[fuel];
     out5[3] = FBP_Q[fuel]; out5[4] = FBP_BUI0[fuel];
     return 0;
 }
 
+int oracle_crown_coefficients(int32_t fuel, double* out2) {
+    if (fuel < 1 || fuel >= NFUEL || !out2) return -1;
+    out2[0] = FBP_CBH[fuel];
+    out2[1] = FBP_CFL[fuel];
+    return 0;
+}
+
 /* ------------------------------------------------------ FBP System model */
+
+/* Landscape-wide FBP inputs: percent conifer (M-1/M-2), grass curing
+ * (O-1), foliar moisture content (C-6 crown fire, crown fraction burned)
+ * and percent dead fir (M-3/M-4), all in percent. */
+typedef struct {
+    double pc, cur, fmc, pdf;
+} fbpland_t;
 
 /* Fine fuel moisture content from FFMC, and the fine-fuel function f(F). */
 static double fine_fuel_fn(double ffmc) {
@@ -101,16 +129,20 @@ static double curing_factor(double c) {
     return 0.176 + 0.02 * (c - 58.8);
 }
 
-/* RSI for any fuel code.  M-1/M-2 mix C-2 and D-1 by percent conifer
- * (M-2 takes 0.2 of the D-1 rate); O-1 is scaled by the curing factor;
- * C-6 uses its surface curve only (no crown fraction). */
-static double rsi_fuel(int f, double isi, double pc, double cur) {
-    double w = pc / 100.0;
+/* RSI for any fuel code.  M-1/M-2 mix C-2 and D-1 by percent conifer, M-3
+ * /M-4 mix their dead-fir curve and D-1 by percent dead fir (M-2 and M-4
+ * take 0.2 of the D-1 rate, the leaf-on stands); O-1 is scaled by the
+ * curing factor; C-6 here is its surface curve (the crown part is added in
+ * fbp_eval); D-2 has its own curve (a fifth of D-1's). */
+static double rsi_fuel(int f, double isi, const fbpland_t* P) {
+    double w = P->pc / 100.0, d = P->pdf / 100.0;
     switch (f) {
         case M1: return w * rsi_pure(C2, isi) + (1.0 - w) * rsi_pure(D1, isi);
         case M2: return w * rsi_pure(C2, isi) + 0.2 * (1.0 - w) * rsi_pure(D1, isi);
+        case M3: return d * rsi_pure(M3, isi) + (1.0 - d) * rsi_pure(D1, isi);
+        case M4: return d * rsi_pure(M4, isi) + 0.2 * (1.0 - d) * rsi_pure(D1, isi);
         case O1A:
-        case O1B: return rsi_pure(f, isi) * curing_factor(cur);
+        case O1B: return rsi_pure(f, isi) * curing_factor(P->cur);
         default: return rsi_pure(f, isi);
     }
 }
@@ -129,18 +161,23 @@ static double isf_pure(int f, double rsf, double cf) {
     return log(t) / (-FBP_B[f]);
 }
 
-/* Slope-adjusted zero-wind spread index ISF.  Mixedwood: percent-conifer
- * weighted ISF of the pure C-2 and D-1 curves. */
-static double isf_fuel(int f, double sf, double isz, double pc, double cur) {
-    double w = pc / 100.0;
+/* Slope-adjusted zero-wind spread index ISF.  Mixedwoods: the weighted ISF
+ * of their two pure curves (percent conifer for M-1/M-2 over C-2 and D-1,
+ * percent dead fir for M-3/M-4 over their own curve and D-1). */
+static double isf_fuel(int f, double sf, double isz, const fbpland_t* P) {
+    double w = P->pc / 100.0, d = P->pdf / 100.0;
     switch (f) {
         case M1:
         case M2:
             return w * isf_pure(C2, sf * rsi_pure(C2, isz), 1.0) +
                    (1.0 - w) * isf_pure(D1, sf * rsi_pure(D1, isz), 1.0);
+        case M3:
+        case M4:
+            return d * isf_pure(f, sf * rsi_pure(f, isz), 1.0) +
+                   (1.0 - d) * isf_pure(D1, sf * rsi_pure(D1, isz), 1.0);
         case O1A:
         case O1B: {
-            double cf = curing_factor(cur);
+            double cf = curing_factor(P->cur);
             return isf_pure(f, sf * rsi_pure(f, isz) * cf, cf);
         }
         default: return isf_pure(f, sf * rsi_pure(f, isz), 1.0);
@@ -148,10 +185,10 @@ static double isf_fuel(int f, double sf, double isz, double pc, double cur) {
 }
 
 /* Slope-equivalent wind speed WSE (km/h) for slope gs (percent). */
-static double slope_equiv_wind(int f, double gs, double ff, double pc, double cur) {
+static double slope_equiv_wind(int f, double gs, double ff, const fbpland_t* P) {
     double sf = (gs >= 70.0) ? 10.0 : exp(3.533 * pow(gs / 100.0, 1.2));
     double isz = 0.208 * ff;
-    double isf = isf_fuel(f, sf, isz, pc, cur);
+    double isf = isf_fuel(f, sf, isz, P);
     double wse = log(isf / isz) / 0.05039;
     if (wse > 40.0) {
         if (isf < 0.999 * 2.496 * ff) wse = 28.0 - log(1.0 - isf / (2.496 * ff)) / 0.0818;
@@ -160,18 +197,73 @@ static double slope_equiv_wind(int f, double gs, double ff, double pc, double cu
     return wse;
 }
 
+/* Surface fuel consumption (kg/m^2) from FFMC and BUI. */
+static double surface_fuel_consumption(int f, double ffmc, double bui, const fbpland_t* P) {
+    switch (f) {
+        case C1:
+            return ffmc > 84.0 ? 0.75 + 0.75 * sqrt(1.0 - exp(-0.23 * (ffmc - 84.0)))
+                               : 0.75 - 0.75 * sqrt(1.0 - exp(-0.23 * (84.0 - ffmc)));
+        case C2:
+        case M3:
+        case M4: return 5.0 * (1.0 - exp(-0.0115 * bui));
+        case C3:
+        case C4: return 5.0 * pow(1.0 - exp(-0.0164 * bui), 2.24);
+        case C5:
+        case C6: return 5.0 * pow(1.0 - exp(-0.0149 * bui), 2.48);
+        case C7: {
+            double ffc = ffmc > 70.0 ? 2.0 * (1.0 - exp(-0.104 * (ffmc - 70.0))) : 0.0;
+            return ffc + 1.5 * (1.0 - exp(-0.0201 * bui));
+        }
+        case D1:
+        case D2: return 1.5 * (1.0 - exp(-0.0183 * bui));
+        case M1:
+        case M2: {
+            double w = P->pc / 100.0;
+            return w * 5.0 * (1.0 - exp(-0.0115 * bui)) + (1.0 - w) * 1.5 * (1.0 - exp(-0.0183 * bui));
+        }
+        case S1: return 4.0 * (1.0 - exp(-0.025 * bui)) + 4.0 * (1.0 - exp(-0.034 * bui));
+        case S2: return 10.0 * (1.0 - exp(-0.013 * bui)) + 6.0 * (1.0 - exp(-0.060 * bui));
+        case S3: return 12.0 * (1.0 - exp(-0.0166 * bui)) + 20.0 * (1.0 - exp(-0.0210 * bui));
+        case O1A:
+        case O1B: return GRASS_FUEL_LOAD;
+        default: return 0.0;
+    }
+}
+
+/* Critical surface fire intensity for crowning (kW/m) and the surface rate
+ * it takes (m/min); the crown fraction burned at surface rate ros. */
+static double critical_surface_rate(int f, double fmc, double sfc) {
+    double csi = 0.001 * pow(FBP_CBH[f], 1.5) * pow(460.0 + 25.9 * fmc, 1.5);
+    return sfc > 0.0 ? csi / (300.0 * sfc) : INFINITY;
+}
+
+static double crown_fraction(double ros, double rso) {
+    return ros > rso ? 1.0 - exp(-0.23 * (ros - rso)) : 0.0;
+}
+
+/* C-6 crown fire rate at spread index isi: 60 (1 - exp(-0.0497 ISI)) scaled
+ * by the foliar moisture effect relative to its average 0.778. */
+static double c6_crown_rate(double isi, double fmc) {
+    double fme = 1000.0 * pow(1.5 - 0.00275 * fmc, 4.0) / (460.0 + 25.9 * fmc);
+    return 60.0 * (1.0 - exp(-0.0497 * isi)) * fme / 0.778;
+}
+
 typedef struct {
-    double hros, bros, fros, lb, raz, isi, wsv, be, rsi, wse;
+    double hros, bros, fros, lb, raz, isi, wsv, be, rsi, wse, sfc, cfb, tfc, hfi;
 } fbp_t;
 
-/* Head, back and flank rates, length-to-breadth ratio and spread azimuth.
- * Wind direction wd is the azimuth the wind blows FROM; the fire heads
- * downwind (wd + 180).  Slope enters through the slope-equivalent wind,
- * added as a vector along the upslope azimuth saz. */
+/* Head, back and flank rates, length-to-breadth ratio and spread azimuth,
+ * and the head fire's fuel consumption and intensity.  Wind direction wd is
+ * the azimuth the wind blows FROM; the fire heads downwind (wd + 180).  Slope
+ * enters through the slope-equivalent wind, added as a vector along the
+ * upslope azimuth saz.  C-6 adds its crown fire to the surface rate: ROS =
+ * RSS + CFB (RSC - RSS) with CFB from the surface rate.  Crown fraction
+ * burned, total fuel consumption SFC + CFB CFL and head fire intensity
+ * 300 TFC ROS (kW/m) follow the head rate (the surface rate for C-6). */
 static void fbp_eval(int f, double ffmc, double bui, double ws, double wd, double gs,
-                     double saz, double pc, double cur, fbp_t* o) {
+                     double saz, const fbpland_t* P, fbp_t* o) {
     double ff = fine_fuel_fn(ffmc);
-    double wse = (gs > 0.0) ? slope_equiv_wind(f, gs, ff, pc, cur) : 0.0;
+    double wse = (gs > 0.0) ? slope_equiv_wind(f, gs, ff, P) : 0.0;
     double waz = fmod(wd + 180.0, 360.0);
     double wsx = ws * sin(waz * D2R) + wse * sin(saz * D2R);
     double wsy = ws * cos(waz * D2R) + wse * cos(saz * D2R);
@@ -186,10 +278,21 @@ static void fbp_eval(int f, double ffmc, double bui, double ws, double wd, doubl
     }
     double isi = 0.208 * wind_fn(wsv) * ff;
     double be = bui_effect(f, bui);
-    double rsi = rsi_fuel(f, isi, pc, cur);
+    double rsi = rsi_fuel(f, isi, P);
     double hros = rsi * be;
     double bisi = 0.208 * exp(-0.05039 * wsv) * ff;
-    double bros = rsi_fuel(f, bisi, pc, cur) * be;
+    double bros = rsi_fuel(f, bisi, P) * be;
+    double sfc = surface_fuel_consumption(f, ffmc, bui, P);
+    double rso = critical_surface_rate(f, P->fmc, sfc);
+    double cfb = 0.0;
+    if (f == C6) {
+        double rss = hros, brss = bros;
+        cfb = crown_fraction(rss, rso);
+        hros = rss + cfb * (c6_crown_rate(isi, P->fmc) - rss);
+        bros = brss + crown_fraction(brss, rso) * (c6_crown_rate(bisi, P->fmc) - brss);
+    } else if (FBP_CFL[f] > 0.0) {
+        cfb = crown_fraction(hros, rso);
+    }
     double lb;
     if (f == O1A || f == O1B) lb = (wsv >= 1.0) ? 1.1 * pow(wsv, 0.464) : 1.0;
     else lb = 1.0 + 8.729 * pow(1.0 - exp(-0.030 * wsv), 2.155);
@@ -203,16 +306,33 @@ static void fbp_eval(int f, double ffmc, double bui, double ws, double wd, doubl
     o->be = be;
     o->rsi = rsi;
     o->wse = wse;
+    o->sfc = sfc;
+    o->cfb = cfb;
+    o->tfc = sfc + cfb * FBP_CFL[f];
+    o->hfi = 300.0 * o->tfc * hros;
+}
+
+int oracle_fbp_point_ext(int32_t fuel, double ffmc, double bui, double ws_kmh, double wd_from_deg,
+                         double slope_pct, double upslope_az_deg, double pc_pct, double curing_pct,
+                         double fmc_pct, double pdf_pct, double* out) {
+    if (fuel < 1 || fuel >= NFUEL || !out) return -1;
+    fbpland_t P = {pc_pct, curing_pct, fmc_pct, pdf_pct};
+    fbp_t o;
+    fbp_eval(fuel, ffmc, bui, ws_kmh, wd_from_deg, slope_pct, upslope_az_deg, &P, &o);
+    out[0] = o.hros; out[1] = o.bros; out[2] = o.fros; out[3] = o.lb; out[4] = o.raz;
+    out[5] = o.isi; out[6] = o.wsv; out[7] = o.be; out[8] = o.rsi; out[9] = o.wse;
+    out[10] = o.sfc; out[11] = o.cfb; out[12] = o.tfc; out[13] = o.hfi;
+    return 0;
 }
 
 int oracle_fbp_point(int32_t fuel, double ffmc, double bui, double ws_kmh, double wd_from_deg,
                      double slope_pct, double upslope_az_deg, double pc_pct, double curing_pct,
                      double* out) {
-    if (fuel < 1 || fuel > 15 || !out) return -1;
-    fbp_t o;
-    fbp_eval(fuel, ffmc, bui, ws_kmh, wd_from_deg, slope_pct, upslope_az_deg, pc_pct, curing_pct, &o);
-    out[0] = o.hros; out[1] = o.bros; out[2] = o.fros; out[3] = o.lb; out[4] = o.raz;
-    out[5] = o.isi; out[6] = o.wsv; out[7] = o.be; out[8] = o.rsi; out[9] = o.wse;
+    double o[14];
+    if (oracle_fbp_point_ext(fuel, ffmc, bui, ws_kmh, wd_from_deg, slope_pct, upslope_az_deg, pc_pct,
+                             curing_pct, 97.0, 50.0, o))
+        return -1;
+    memcpy(out, o, 10 * sizeof(double));
     return 0;
 }
 
@@ -247,7 +367,7 @@ typedef struct {
     int32_t rows, cols, cell_m;
     const uint8_t* fuel;
     const int16_t* elev;
-    double pc, cur;
+    fbpland_t P;
     int32_t n_scen, n_wp;
     const float* weather;
     int32_t d[8]; /* centre-to-centre distance per axis, integer metres */
@@ -298,7 +418,7 @@ static int neighbour(const land_t* L, int cell, int k) {
 /* ------------------------------------------------ per (cell, period) rates */
 
 typedef struct {
-    double h, b, f, lb, raz, mu;
+    double h, b, f, lb, raz, mu, cfb, hfi;
     double x[8], xu[8];
     int32_t q[8];
 } cellros_t;
@@ -318,8 +438,7 @@ static void cell_fbp(const land_t* L, int cell, int scen, int period, fbp_t* o) 
     const float* w = L->weather + ((size_t)scen * L->n_wp + period) * 4;
     double gs, saz;
     cell_slope(L, cell, &gs, &saz);
-    fbp_eval(L->fuel[cell], (double)w[0], (double)w[1], (double)w[2], (double)w[3], gs, saz, L->pc,
-             L->cur, o);
+    fbp_eval(L->fuel[cell], (double)w[0], (double)w[1], (double)w[2], (double)w[3], gs, saz, &L->P, o);
 }
 
 static void cell_ros(const land_t* L, int cell, int scen, int period, int rep, uint64_t seed,
@@ -347,6 +466,10 @@ static void cell_ros(const land_t* L, int cell, int scen, int period, int rep, u
     out->lb = o.lb;
     out->raz = o.raz;
     out->mu = mu;
+    /* the multiplier scales the spread rate; the fuel consumed (and so the
+     * crown fraction burned) is the FBP System's own */
+    out->cfb = o.cfb;
+    out->hfi = o.hfi * mu;
     for (int k = 0; k < 8; ++k) {
         out->x[k] = mu * ros[k];
         out->xu[k] = out->x[k] + u[k];
@@ -357,13 +480,14 @@ static void cell_ros(const land_t* L, int cell, int scen, int period, int rep, u
 /* ------------------------------------------------------------ validation */
 
 static int check_land(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
-                      double pc, double cur, int32_t n_scen, int32_t n_wp, const float* weather) {
+                      const fbpland_t* P, int32_t n_scen, int32_t n_wp, const float* weather) {
     if (rows <= 0 || cols <= 0 || cell_m <= 0 || cell_m > 20000 || !fuel || !weather) return -1;
     if ((int64_t)rows * cols > 0x7FFFFFFEll) return -1;
-    if (!(pc >= 0.0 && pc <= 100.0) || !(cur > 0.0 && cur <= 100.0)) return -1;
+    if (!(P->pc >= 0.0 && P->pc <= 100.0) || !(P->cur > 0.0 && P->cur <= 100.0)) return -1;
+    if (!(P->fmc > 0.0 && P->fmc <= 300.0) || !(P->pdf >= 0.0 && P->pdf <= 100.0)) return -1;
     if (n_scen <= 0 || n_wp <= 0) return -1;
     for (int64_t i = 0; i < (int64_t)rows * cols; ++i)
-        if (fuel[i] > 15) return -1;
+        if (fuel[i] >= NFUEL) return -1;
     for (int64_t i = 0; i < (int64_t)n_scen * n_wp; ++i) {
         const float* w = weather + i * 4;
         if (!(w[0] >= 0.0f && w[0] <= 101.0f) || !(w[1] >= 0.0f) || !(w[2] >= 0.0f) ||
@@ -374,10 +498,10 @@ static int check_land(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t*
 }
 
 static void init_land(land_t* L, int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
-                      const int16_t* elev, double pc, double cur, int32_t n_scen, int32_t n_wp,
+                      const int16_t* elev, const fbpland_t* P, int32_t n_scen, int32_t n_wp,
                       const float* weather) {
     L->rows = rows; L->cols = cols; L->cell_m = cell_m; L->fuel = fuel; L->elev = elev;
-    L->pc = pc; L->cur = cur; L->n_scen = n_scen; L->n_wp = n_wp; L->weather = weather;
+    L->P = *P; L->n_scen = n_scen; L->n_wp = n_wp; L->weather = weather;
     /* Orthogonal neighbours sit one cell width away; diagonal ones sqrt(2)
      * widths, rounded up to whole metres (least D with D*D >= 2 cs^2). */
     int64_t two = 2ll * cell_m * cell_m;
@@ -393,23 +517,24 @@ int oracle_eval_ros(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
                     int32_t rounding, double* hros, double* bros, double* fros, double* lb,
                     double* raz, double* x8, double* xu8, int32_t* q8) {
-    return oracle_eval_ros_cells(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
-                                 weather, scenario, period, rep, seed, sigma, rounding, -1, NULL, hros, bros,
-                                 fros, lb, raz, x8, xu8, q8);
+    return oracle_eval_ros_cells(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, 97.0, 50.0, n_scen,
+                                 n_wperiods, weather, scenario, period, rep, seed, sigma, rounding, -1, NULL,
+                                 hros, bros, fros, lb, raz, x8, xu8, q8, NULL, NULL);
 }
 
 int oracle_eval_ros_cells(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
-                          const int16_t* elev, double pc_pct, double curing_pct,
-                          int32_t n_scen, int32_t n_wperiods, const float* weather,
+                          const int16_t* elev, double pc_pct, double curing_pct, double fmc_pct,
+                          double pdf_pct, int32_t n_scen, int32_t n_wperiods, const float* weather,
                           int32_t scenario, int32_t period, int32_t rep, uint64_t seed, double sigma,
                           int32_t rounding, int64_t n_cells, const int32_t* cells, double* hros,
                           double* bros, double* fros, double* lb, double* raz, double* x8, double* xu8,
-                          int32_t* q8) {
-    if (check_land(rows, cols, cell_m, fuel, pc_pct, curing_pct, n_scen, n_wperiods, weather)) return -1;
+                          int32_t* q8, double* cfb, double* hfi) {
+    const fbpland_t P = {pc_pct, curing_pct, fmc_pct, pdf_pct};
+    if (check_land(rows, cols, cell_m, fuel, &P, n_scen, n_wperiods, weather)) return -1;
     if (scenario < 0 || scenario >= n_scen || period < 0 || period >= n_wperiods || rep < 0) return -1;
     if (!(sigma >= 0.0) || (rounding != 0 && rounding != 1)) return -1;
     land_t L;
-    init_land(&L, rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods, weather);
+    init_land(&L, rows, cols, cell_m, fuel, elev, &P, n_scen, n_wperiods, weather);
     const int64_t n = cells ? n_cells : (int64_t)rows * cols;
     for (int64_t k = 0; k < n; ++k) {
         if (cells && (cells[k] < 0 || (int64_t)cells[k] >= (int64_t)rows * cols)) return -1;
@@ -427,6 +552,8 @@ int oracle_eval_ros_cells(int32_t rows, int32_t cols, int32_t cell_m, const uint
         if (fros) fros[o] = c.f;
         if (lb) lb[o] = c.lb;
         if (raz) raz[o] = c.raz;
+        if (cfb) cfb[o] = c.cfb;
+        if (hfi) hfi[o] = c.hfi;
         for (int k = 0; k < 8; ++k) {
             if (x8) x8[o * 8 + k] = c.x[k];
             if (xu8) xu8[o * 8 + k] = c.xu[k];
@@ -485,10 +612,10 @@ int oracle_simulate(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* f
                     uint8_t* scar, int32_t* arrival_period, int32_t* arrival_minute,
                     uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
                     int32_t* scenario_out, int64_t* stats) {
-    return oracle_simulate_ext(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods,
-                               period_min, weather, reps, rep_offset, n_periods, seed, sigma, threshold,
-                               rounding, ignition_mode, ignition_cell, NULL, 0, 0, 0.0, 0, NULL, scenario_mode,
-                               scenario_fixed, n_override, override_key, override_q, scar, arrival_period,
+    return oracle_simulate_ext(rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, 97.0, 50.0, n_scen,
+                               n_wperiods, period_min, weather, reps, rep_offset, n_periods, seed, sigma,
+                               threshold, rounding, ignition_mode, ignition_cell, NULL, 0, 0, 0.0, 0.0, 0, NULL,
+                               scenario_mode, scenario_fixed, n_override, override_key, override_q, scar, arrival_period,
                                arrival_minute, burn_count, burned_cells, ignition_out, scenario_out, stats);
 }
 
@@ -501,12 +628,12 @@ static int burning_minute(int32_t m, int32_t burn_hours) {
 }
 
 int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_t* fuel,
-                        const int16_t* elev, double pc_pct, double curing_pct,
-                        int32_t n_scen, int32_t n_wperiods, int32_t period_min, const float* weather,
-                        int32_t reps, int32_t rep_offset, int32_t n_periods, uint64_t seed,
-                        double sigma, double threshold, int32_t rounding,
+                        const int16_t* elev, double pc_pct, double curing_pct, double fmc_pct,
+                        double pdf_pct, int32_t n_scen, int32_t n_wperiods, int32_t period_min,
+                        const float* weather, int32_t reps, int32_t rep_offset, int32_t n_periods,
+                        uint64_t seed, double sigma, double threshold, int32_t rounding,
                         int32_t ignition_mode, int32_t ignition_cell, const uint32_t* ignition_weights,
-                        int32_t ignition_period, int32_t burn_hours, double burnout_ros,
+                        int32_t ignition_period, int32_t burn_hours, double burnout_ros, double hfi_min,
                         int32_t n_ignitions, const int32_t* ignition_list,
                         int32_t scenario_mode, int32_t scenario_fixed,
                         int32_t n_override, const int32_t* override_key, const int32_t* override_q,
@@ -514,7 +641,9 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         uint32_t* burn_count, int64_t* burned_cells, int32_t* ignition_out,
                         int32_t* scenario_out, int64_t* stats) {
     if (!(burnout_ros >= 0.0) || !isfinite(burnout_ros)) return -1;
-    if (check_land(rows, cols, cell_m, fuel, pc_pct, curing_pct, n_scen, n_wperiods, weather)) return -1;
+    if (!(hfi_min >= 0.0) || !isfinite(hfi_min)) return -1;
+    const fbpland_t FP = {pc_pct, curing_pct, fmc_pct, pdf_pct};
+    if (check_land(rows, cols, cell_m, fuel, &FP, n_scen, n_wperiods, weather)) return -1;
     if (reps <= 0 || rep_offset < 0 || n_periods <= 0 || n_periods > n_wperiods || period_min <= 0)
         return -1;
     if ((int64_t)n_periods * period_min > 0x7FFFFFF0ll) return -1;
@@ -537,7 +666,7 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
     if (n_override < 0 || (n_override > 0 && (!override_key || !override_q))) return -1;
 
     land_t L;
-    init_land(&L, rows, cols, cell_m, fuel, elev, pc_pct, curing_pct, n_scen, n_wperiods, weather);
+    init_land(&L, rows, cols, cell_m, fuel, elev, &FP, n_scen, n_wperiods, weather);
     const int32_t P = period_min;
     const int32_t T = n_periods * period_min;
 
@@ -716,15 +845,17 @@ int oracle_simulate_ext(int32_t rows, int32_t cols, int32_t cell_m, const uint8_
                         }
                     }
                     const int32_t* oq = ov.n ? override_find(&ov, rep, p, b->cell) : NULL;
-                    if (oq) {
-                        for (int k = 0; k < 8; ++k) b->q[k] = oq[k];
-                    } else {
-                        cellros_t c;
+                    cellros_t c;
+                    if (!oq || hfi_min > 0.0) {
                         cell_ros(&L, b->cell, scen, p, rep, seed, sigma, rounding, &c);
-                        for (int k = 0; k < 8; ++k) b->q[k] = c.q[k];
                         ++st_fbp;
                     }
+                    for (int k = 0; k < 8; ++k) b->q[k] = oq ? oq[k] : c.q[k];
                     b->qperiod = p;
+                    /* burn-out (A5 iv): a head fire intensity below the
+                     * user's threshold makes the cell unavailable */
+                    if (hfi_min > 0.0 && c.hfi < hfi_min)
+                        for (int k = 0; k < 8; ++k) b->prog[k] = L.d[k];
                     /* burn-out (A5 i): when the rates toward every burnable
                      * neighbour fall below delta the cell stops spreading */
                     if (burnout_ros > 0.0) {

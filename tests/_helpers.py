@@ -12,7 +12,7 @@ def oracle_run(fuel, elev, weather, *, n_periods, reps=1, rep_offset=0, seed=0, 
                threshold=0.0, rounding=0, ignition_mode=0, ignition_cell=0, scenario_mode=0,
                scenario=0, period_min=60, cell_m=100, pc=50.0, curing=80.0, overrides=None,
                want_rep_outputs=True, ignition_weights=None, ignition_period=0, burn_hours=0,
-               burnout=0.0, ignitions=None):
+               burnout=0.0, ignitions=None, fmc=97.0, pdf=50.0, hfi_min=0.0):
     return oracle.simulate(fuel, elev, weather, cell_m=cell_m, n_periods=n_periods, reps=reps,
                            rep_offset=rep_offset, seed=seed, sigma=np.float32(sigma).item(),
                            threshold=np.float32(threshold).item(), rounding=rounding,
@@ -21,7 +21,9 @@ def oracle_run(fuel, elev, weather, *, n_periods, reps=1, rep_offset=0, seed=0, 
                            pc=np.float32(pc).item(), curing=np.float32(curing).item(),
                            overrides=overrides, want_rep_outputs=want_rep_outputs,
                            ignition_weights=ignition_weights, ignition_period=ignition_period,
-                           burn_hours=burn_hours, burnout=np.float32(burnout).item(), ignitions=ignitions)
+                           burn_hours=burn_hours, burnout=np.float32(burnout).item(), ignitions=ignitions,
+                           fmc=np.float32(fmc).item(), pdf=np.float32(pdf).item(),
+                           hfi_min=np.float32(hfi_min).item())
 
 
 def assert_same_outputs(gpu: dict, ref: dict, names=OUTS, where=""):

@@ -362,7 +362,7 @@ def test_invalid_inputs_rejected():
     with pytest.raises(ValueError):
         oracle.simulate(fuel, None, wx, n_periods=3)          # more periods than weather
     bad = fuel.copy()
-    bad[0, 0] = 16
+    bad[0, 0] = 19   # codes run to 18 (M-4)
     with pytest.raises(ValueError):
         oracle.simulate(bad, None, wx, n_periods=1)
     with pytest.raises(ValueError):
