@@ -22,7 +22,8 @@
  *     i = row * cols + col.  Axis order everywhere: E, NE, N, NW, W, SW, S,
  *     SE (0 deg = East, counter-clockwise, Section 3.4 step i).
  *   - Fuel codes: 0 non-fuel, 1-7 C-1..C-7, 8 D-1, 9 M-1, 10 M-2,
- *     11-13 S-1..S-3, 14 O-1a, 15 O-1b (Table FBPT gives the dictionary idea).
+ *     11-13 S-1..S-3, 14 O-1a, 15 O-1b, 16 D-2, 17 M-3, 18 M-4 (Table FBPT
+ *     gives the dictionary idea; Section 2.3 lists the FBP fuel types).
  *   - Every function returns a c2f_status; nothing is thrown or aborted
  *     across the ABI.  On failure, outputs are not written and
  *     c2f_last_error() describes the cause.
@@ -86,6 +87,16 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
                               const uint8_t* fuel, const int16_t* elev_m, float pc_pct,
                               float curing_pct, int32_t* landscape_id);
 c2f_status c2f_unload_landscape(c2f_ctx* ctx, int32_t landscape_id);
+
+/* FBP inputs of a loaded landscape besides percent conifer and curing
+ * (Section 2.3: the FBP System's fuel moisture and stand descriptors):
+ * foliar moisture content fmc_pct (0 < FMC <= 300; default 97, where the C-6
+ * foliar moisture effect equals its average) for C-6 crown fire and the
+ * crown fraction burned of every crowning fuel, and percent dead fir
+ * pdf_pct (0..100, default 50) of M-3/M-4 stands.  Derived landscapes take
+ * their base's values.  EBUSY while the landscape is used by submitted
+ * requests. */
+c2f_status c2f_set_landscape_fbp(c2f_ctx* ctx, int32_t landscape_id, float fmc_pct, float pdf_pct);
 
 /* A treatment variant of a loaded landscape (Section 1: harvested or
  * non-fuel cells as fuel-management plans): a new landscape with the base's
@@ -196,7 +207,14 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *                  while entries remain.  ignition_period is unused, and the
  *                  replication's reported ignition is the cell of the
  *                  earliest entry (the first listed among entries of one
- *                  period).  Other modes need n_ignitions = 0. */
+ *                  period).  Other modes need n_ignitions = 0.
+ *   hfi_min        head fire intensity threshold (kW/m; assumption A5 (iv);
+ *                  0 = off): when a burning cell's rates are evaluated for a
+ *                  period and its head fire intensity 300 TFC ROS (total
+ *                  fuel consumption from the FBP System, ROS the head rate
+ *                  with the noise multiplier) is below it, it spreads no
+ *                  further, in that period or later.  In precision 1 the
+ *                  intensity is compared in FP32. */
 typedef struct {
     int32_t landscape_id, weather_id, reps, n_periods;
     uint64_t seed;
@@ -209,6 +227,7 @@ typedef struct {
     float burnout_ros;
     int32_t n_ignitions;
     const int32_t* ignition_list;
+    float hfi_min;
 } c2f_sim_params;
 
 /* Outputs of a simulation (Section 3.6 (i) burn grids and their counts).
@@ -281,16 +300,22 @@ c2f_status c2f_count_work(c2f_ctx* ctx, const c2f_sim_params* params, const int3
  * be NULL, each [rows*cols] (q8 and x8: [rows*cols][8]):
  * hros/bros/fros m/min including the rep's noise multiplier, lb, raz_deg
  * (spread azimuth, clockwise from north), x8 the unquantised axis rates
- * (eq. (1) times the multiplier), q8 the integer axis rates.  Non-fuel
- * cells give zeros. */
+ * (eq. (1) times the multiplier), q8 the integer axis rates, cfb the crown
+ * fraction burned and hfi the head fire intensity (kW/m, with the
+ * multiplier on the rate).  Non-fuel cells give zeros. */
 c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, int32_t scenario,
                         int32_t period, int32_t rep, uint64_t seed, float sigma, int32_t rounding,
                         int32_t precision, double* hros, double* bros, double* fros, double* lb,
-                        double* raz_deg, double* x8, int32_t* q8);
+                        double* raz_deg, double* x8, int32_t* q8, double* cfb, double* hfi);
 
-/* FBP coefficients (a, b, c, q, BUI0) of fuel code 1..15 as the device uses
- * them (M-1/M-2 report zeros for a, b, c).  Host-only, needs no device. */
+/* FBP coefficients (a, b, c, q, BUI0) of fuel code 1..18 as the device uses
+ * them (M-1/M-2 report zeros for a, b, c; M-3/M-4 their dead-fir curves).
+ * Host-only, needs no device. */
 c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]);
+
+/* Crown base height (m) and crown fuel load (kg/m^2) of fuel code 1..18
+ * (zeros for fuels that do not crown).  Host-only. */
+c2f_status c2f_fbp_crown_coefficients(int32_t fuel, double out2[2]);
 
 /* Tuning.  block_threads: threads per work group of the propagation kernel
  * (one of 64, 128, 256, 512, 768, 1024; 0 = automatic).  list_capacity: least number

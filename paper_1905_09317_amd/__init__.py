@@ -3,4 +3,4 @@
 The simulation runs in libc2f.so (hand-written HIP kernels behind the C ABI
 of include/c2f.h); this package only marshals arguments.
 """
-from .api import C2FError, Request, Simulator, fbp_coefficients, request_for  # noqa: F401
+from .api import C2FError, Request, Simulator, fbp_coefficients, fbp_crown_coefficients, request_for  # noqa: F401

@@ -28,7 +28,8 @@ class SimParams(ctypes.Structure):
                 ("scenario_mode", ctypes.c_int32), ("scenario", ctypes.c_int32),
                 ("rep_offset", ctypes.c_int32), ("ignition_period", ctypes.c_int32),
                 ("burn_hours", ctypes.c_int32), ("burnout_ros", ctypes.c_float),
-                ("n_ignitions", ctypes.c_int32), ("ignition_list", ctypes.c_void_p)]
+                ("n_ignitions", ctypes.c_int32), ("ignition_list", ctypes.c_void_p),
+                ("hfi_min", ctypes.c_float)]
 
 
 class Outputs(ctypes.Structure):
@@ -88,8 +89,10 @@ def load() -> ctypes.CDLL:
         "c2f_simulate_batch": ([P, i32, pp(SimParams), pp(Outputs)], i32),
         "c2f_simulate_noalloc": ([P, pp(SimParams), pp(Outputs)], i32),
         "c2f_count_work": ([P, pp(SimParams), P, P], i32),
-        "c2f_eval_ros": ([P, i32, i32, i32, i32, i32, u64, f32, i32, i32, P, P, P, P, P, P, P], i32),
+        "c2f_eval_ros": ([P, i32, i32, i32, i32, i32, u64, f32, i32, i32, P, P, P, P, P, P, P, P, P], i32),
         "c2f_fbp_coefficients": ([i32, P], i32),
+        "c2f_fbp_crown_coefficients": ([i32, P], i32),
+        "c2f_set_landscape_fbp": ([P, i32, f32, f32], i32),
         "c2f_set_tuning": ([P, i32, i64], i32),
         "c2f_autotune": ([P, pp(SimParams)], i32),
         "c2f_get_stats": ([P, pp(RunStats)], i32),
@@ -115,7 +118,8 @@ def load() -> ctypes.CDLL:
 
 DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2f_load_landscape",
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
-            "c2f_simulate_batch", "c2f_simulate_noalloc", "c2f_count_work", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_set_tuning",
+            "c2f_simulate_batch", "c2f_simulate_noalloc", "c2f_count_work", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_fbp_crown_coefficients",
+            "c2f_set_landscape_fbp", "c2f_set_tuning",
             "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
             "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_rep_order",
             "c2f_set_ignition_map", "c2f_derive_landscape", "c2f_compare_scars",

@@ -45,6 +45,7 @@ class Request:
     ignition_period: int = 0
     burn_hours: int = 0
     burnout: float = 0.0
+    hfi_min: float = 0.0      # head fire intensity below which a burning cell burns out (kW/m; 0 = off)
     outputs: tuple = OUTPUT_NAMES
     device_out: bool = False
     ignitions: object = None   # (cell, period) pairs: the ignition-point list (ignition_mode 4)
@@ -59,7 +60,7 @@ class Request:
                          int(self.seed) & (2**64 - 1), float(self.sigma), float(self.threshold),
                          self.rounding, self.precision, mode, self.ignition_cell,
                          self.scenario_mode, self.scenario, self.rep_offset, self.ignition_period,
-                         self.burn_hours, float(self.burnout), n, ptr)
+                         self.burn_hours, float(self.burnout), n, ptr, float(self.hfi_min))
 
 
 @dataclass
@@ -308,15 +309,20 @@ class Simulator:
                  sigma=0.0, rounding=0, precision=0) -> dict:
         lm = self._lands[landscape]
         n = lm.rows * lm.cols
-        out = {k: np.empty(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz")}
+        out = {k: np.empty(n, np.float64) for k in ("hros", "bros", "fros", "lb", "raz", "cfb", "hfi")}
         out["x8"] = np.empty((n, 8), np.float64)
         out["q8"] = np.empty((n, 8), np.int32)
         ptr = {k: v.ctypes.data_as(ctypes.c_void_p) for k, v in out.items()}
         self._check(self._L.c2f_eval_ros(
             self._ctx, int(landscape), int(weather), int(scenario), int(period), int(rep),
             int(seed) & (2**64 - 1), float(sigma), int(rounding), int(precision), ptr["hros"],
-            ptr["bros"], ptr["fros"], ptr["lb"], ptr["raz"], ptr["x8"], ptr["q8"]))
+            ptr["bros"], ptr["fros"], ptr["lb"], ptr["raz"], ptr["x8"], ptr["q8"], ptr["cfb"],
+            ptr["hfi"]))
         return out
+
+    def set_landscape_fbp(self, landscape: int, fmc: float = 97.0, pdf: float = 50.0):
+        """Foliar moisture content and percent dead fir of a landscape."""
+        self._check(self._L.c2f_set_landscape_fbp(self._ctx, int(landscape), float(fmc), float(pdf)))
 
     # ------------------------------------------------------------- tuning
     def set_tuning(self, block_threads: int = 0, list_capacity: int = 0):
@@ -382,6 +388,15 @@ class Simulator:
         finally:
             res = self._keep.pop(ticket, None)
         return res, {k: getattr(info, k) for k, _ in TicketInfo._fields_}
+
+
+def fbp_crown_coefficients(fuel: int) -> np.ndarray:
+    """Crown base height (m) and crown fuel load (kg/m^2) of a fuel code."""
+    out = np.zeros(2, np.float64)
+    st = _lib.load().c2f_fbp_crown_coefficients(int(fuel), out.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise C2FError(st, f"bad fuel code {fuel}")
+    return out
 
 
 def fbp_coefficients(fuel: int) -> np.ndarray:

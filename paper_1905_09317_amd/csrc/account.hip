@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void work_counts_kernel(const Job* __restrict_
         X.rounding = job.rounding;
         X.rep = rep;
         X.burnout = job.burnout;
+        X.hfi_min = job.hfi_min;
         int32_t prog[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         // the cell first spreads in minute a + 1, which lies in period a / P
         for (int p = a / P; p < job.n_periods; ++p) {
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(256) void work_counts_kernel(const Job* __restrict_
             if (!live) break;   // no axis can ever become live again
             ++c_bp;
             int32_t q[8];
-            axis_q<R>(X, rec, (uint32_t)cell, (uint32_t)p, q);
+            if (axis_q<R>(X, rec, (uint32_t)cell, (uint32_t)p, q)) break;   // too faint: burned out
             if (job.burnout > 0.f) {
                 int32_t qmax = 0;
 #pragma unroll

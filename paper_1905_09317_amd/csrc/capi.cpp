@@ -39,6 +39,7 @@ thread_local std::string t_err;
 struct Landscape {
     int32_t rows = 0, cols = 0, cell_m = 0;
     float pc = 50.f, curing = 80.f;
+    float fmc = 97.f, pdf = 50.f;   // foliar moisture content, percent dead fir
     uint8_t* fuel = nullptr;
     CellRec* cells = nullptr;
     int32_t* burnable = nullptr;
@@ -680,6 +681,8 @@ c2f_status check_params(c2f_ctx* ctx, const c2f_sim_params* p, Landscape** L, We
     if (p->burn_hours < 0 || p->burn_hours > 24) return fail(ctx, C2F_EINVAL, "burn_hours must be 0..24");
     if (!(p->burnout_ros >= 0.f) || !std::isfinite(p->burnout_ros))
         return fail(ctx, C2F_EINVAL, "burnout_ros must be finite and >= 0");
+    if (!(p->hfi_min >= 0.f) || !std::isfinite(p->hfi_min))
+        return fail(ctx, C2F_EINVAL, "hfi_min must be finite and >= 0");
     if (p->burn_hours > 0 && p->burn_hours < 24 && (w.period_min > 60 || 60 % w.period_min != 0))
         return fail(ctx, C2F_EINVAL, "burn_hours needs a period length dividing 60 minutes (got %d)",
                     w.period_min);
@@ -787,6 +790,7 @@ Job make_job(const c2f_sim_params& p, const Landscape& L, const Weather& W, cons
     j.ign_total = p.ignition_mode == 3 ? L.ign_total : 0;
     j.burn_hours = (p.burn_hours >= 24) ? 0 : p.burn_hours;
     j.burnout = p.burnout_ros;
+    j.hfi_min = p.hfi_min;
     j.sigma = p.ros_sigma;
     j.threshold = p.ros_threshold;
     j.seed = p.seed;
@@ -1432,7 +1436,8 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     if (!(curing_pct > 0.f && curing_pct <= 100.f)) return fail(ctx, C2F_EINVAL, "curing_pct must be in (0, 100]");
     const int64_t n = (int64_t)rows * cols;
     for (int64_t i = 0; i < n; ++i)
-        if (fuel[i] > 15) return fail(ctx, C2F_EINVAL, "fuel code %d at cell %lld > 15", fuel[i], (long long)i);
+        if (fuel[i] >= kNumFuels)
+            return fail(ctx, C2F_EINVAL, "fuel code %d at cell %lld > %d", fuel[i], (long long)i, kNumFuels - 1);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->main.stream;
     Landscape L;
@@ -1465,8 +1470,8 @@ c2f_status c2f_load_landscape(c2f_ctx* ctx, int32_t rows, int32_t cols, int32_t 
     hipError_t e = hipMemcpyAsync(L.fuel, fuel, (size_t)n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && elev_m) e = hipMemcpyAsync(d_elev, elev_m, (size_t)n * 2, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = launch_prepare_landscape(L.fuel, d_elev, nullptr, rows, cols, cell_m, pc_pct, curing_pct, L.cells, L.burnable,
-                                     d_tiles, L.land, s);
+        e = launch_prepare_landscape(L.fuel, d_elev, nullptr, rows, cols, cell_m, pc_pct, curing_pct, L.fmc, L.pdf,
+                                     L.cells, L.burnable, d_tiles, L.land, s);
     LandDev hl;
     if (e == hipSuccess) e = hipMemcpyAsync(&hl, L.land, sizeof hl, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1508,7 +1513,8 @@ c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, 
     for (int64_t k = 0; k < n_edits; ++k) {
         if (cells[k] < 0 || cells[k] >= n)
             return fail(ctx, C2F_EINVAL, "edit %lld: cell %d outside the grid", (long long)k, cells[k]);
-        if (fuels[k] > 15) return fail(ctx, C2F_EINVAL, "edit %lld: fuel code %d > 15", (long long)k, fuels[k]);
+        if (fuels[k] >= kNumFuels)
+            return fail(ctx, C2F_EINVAL, "edit %lld: fuel code %d > %d", (long long)k, fuels[k], kNumFuels - 1);
     }
     // one edit per cell, the last one given (the device applies them in parallel)
     std::vector<int64_t> order((size_t)n_edits);
@@ -1530,6 +1536,8 @@ c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, 
     L.cell_m = B.cell_m;
     L.pc = B.pc;
     L.curing = B.curing;
+    L.fmc = B.fmc;
+    L.pdf = B.pdf;
     int32_t* d_tiles = nullptr;
     int32_t* d_cells = nullptr;
     uint8_t* d_codes = nullptr;
@@ -1569,8 +1577,8 @@ c2f_status c2f_derive_landscape(c2f_ctx* ctx, int32_t base_id, int64_t n_edits, 
         e = hipMemcpyAsync(d_codes, ucodes.data(), (size_t)n_edits, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_fuel_edits(L.fuel, d_cells, d_codes, n_edits, s);
     if (e == hipSuccess)
-        e = launch_prepare_landscape(L.fuel, nullptr, B.cells, L.rows, L.cols, L.cell_m, L.pc, L.curing, L.cells,
-                                     L.burnable, d_tiles, L.land, s);
+        e = launch_prepare_landscape(L.fuel, nullptr, B.cells, L.rows, L.cols, L.cell_m, L.pc, L.curing, L.fmc,
+                                     L.pdf, L.cells, L.burnable, d_tiles, L.land, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     temps();
     if (e != hipSuccess) {
@@ -1967,7 +1975,8 @@ c2f_status c2f_count_work(c2f_ctx* ctx, const c2f_sim_params* params, const int3
 
 c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, int32_t scenario, int32_t period,
                         int32_t rep, uint64_t seed, float sigma, int32_t rounding, int32_t precision, double* hros,
-                        double* bros, double* fros, double* lb, double* raz_deg, double* x8, int32_t* q8) {
+                        double* bros, double* fros, double* lb, double* raz_deg, double* x8, int32_t* q8,
+                        double* cfb, double* hfi) {
     if (!ctx) return C2F_EINVAL;
     ApiScope api(ctx);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1985,7 +1994,7 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     Exec& ex = ctx->main;
     const size_t n = (size_t)L.ncells();
-    const size_t bytes = n * 8 * 5 + n * 64 + n * 32 + 7 * 256;   // 7 arrays, 256-byte aligned
+    const size_t bytes = n * 8 * 7 + n * 64 + n * 32 + 9 * 256;   // 9 arrays, 256-byte aligned
     c2f_status st = ensure_staging(ctx, ex, bytes);
     if (st != C2F_OK) return st;
     char* sb = (char*)ex.staging;
@@ -2016,6 +2025,8 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
     a.raz = raz_deg ? (double*)take(n * 8) : nullptr;
     a.x8 = x8 ? (double*)take(n * 64) : nullptr;
     a.q8 = q8 ? (int32_t*)take(n * 32) : nullptr;
+    a.cfb = cfb ? (double*)take(n * 8) : nullptr;
+    a.hfi = hfi ? (double*)take(n * 8) : nullptr;
     HIP_TRY(ctx, launch_eval_ros(precision, a, ex.stream));
     if (hros) HIP_TRY(ctx, hipMemcpyAsync(hros, a.hros, n * 8, hipMemcpyDeviceToHost, ex.stream));
     if (bros) HIP_TRY(ctx, hipMemcpyAsync(bros, a.bros, n * 8, hipMemcpyDeviceToHost, ex.stream));
@@ -2024,13 +2035,42 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
     if (raz_deg) HIP_TRY(ctx, hipMemcpyAsync(raz_deg, a.raz, n * 8, hipMemcpyDeviceToHost, ex.stream));
     if (x8) HIP_TRY(ctx, hipMemcpyAsync(x8, a.x8, n * 64, hipMemcpyDeviceToHost, ex.stream));
     if (q8) HIP_TRY(ctx, hipMemcpyAsync(q8, a.q8, n * 32, hipMemcpyDeviceToHost, ex.stream));
+    if (cfb) HIP_TRY(ctx, hipMemcpyAsync(cfb, a.cfb, n * 8, hipMemcpyDeviceToHost, ex.stream));
+    if (hfi) HIP_TRY(ctx, hipMemcpyAsync(hfi, a.hfi, n * 8, hipMemcpyDeviceToHost, ex.stream));
     HIP_TRY(ctx, hipStreamSynchronize(ex.stream));
+    return C2F_OK;
+}
+
+c2f_status c2f_fbp_crown_coefficients(int32_t fuel, double out2[2]) {
+    static const CrownCoef table[kNumFuels] = {C2F_CROWN_ROWS};
+    if (fuel < 1 || fuel >= kNumFuels || !out2) return C2F_EINVAL;
+    out2[0] = table[fuel].cbh;
+    out2[1] = table[fuel].cfl;
+    return C2F_OK;
+}
+
+c2f_status c2f_set_landscape_fbp(c2f_ctx* ctx, int32_t landscape_id, float fmc_pct, float pdf_pct) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, C2F_EDEVICE, "hipSetDevice failed");
+    if (!(fmc_pct > 0.f && fmc_pct <= 300.f)) return fail(ctx, C2F_EINVAL, "fmc_pct must be in (0, 300]");
+    if (!(pdf_pct >= 0.f && pdf_pct <= 100.f)) return fail(ctx, C2F_EINVAL, "pdf_pct must be in [0, 100]");
+    std::lock_guard<std::mutex> lk2(ctx->objmu);
+    auto it = ctx->lands.find(landscape_id);
+    if (it == ctx->lands.end()) return fail(ctx, C2F_ESTATE, "unknown landscape id %d", landscape_id);
+    Landscape& L = it->second;
+    if (L.inflight > 0) return fail(ctx, C2F_EBUSY, "landscape %d is used by submitted requests", landscape_id);
+    HIP_TRY(ctx, launch_fbp_consts(L.land, fmc_pct, pdf_pct, ctx->main.stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->main.stream));
+    L.fmc = fmc_pct;
+    L.pdf = pdf_pct;
     return C2F_OK;
 }
 
 c2f_status c2f_fbp_coefficients(int32_t fuel, double out5[5]) {
     static const FuelCoef table[kNumFuels] = {C2F_FUEL_ROWS};
-    if (fuel < 1 || fuel > 15 || !out5) return C2F_EINVAL;
+    if (fuel < 1 || fuel >= kNumFuels || !out5) return C2F_EINVAL;
     out5[0] = table[fuel].a;
     out5[1] = table[fuel].b;
     out5[2] = table[fuel].c;

@@ -110,7 +110,8 @@ __device__ __forceinline__ R unit24(uint32_t x) {
 // Per (scenario, period) quantities that do not depend on the cell; kept in
 // a table computed once per weather upload.  Layout of one row:
 //   [0] f(F)   [1] ISZ = 0.208 f(F)   [2] WS sin(WAZ)   [3] WS cos(WAZ)
-//   [4 + f] BUI effect of fuel f      [20 + f] 1 - exp(-b_f ISZ) of pure fuel f
+//   [4 + f] BUI effect of fuel f      [23 + f] 1 - exp(-b_f ISZ) of pure fuel f
+//   [42 + f] surface fuel consumption of fuel f
 
 template <typename R>
 struct CoefR {
@@ -121,6 +122,37 @@ struct CoefR {
 template <typename R>
 __device__ __forceinline__ R rsi_pure(const CoefR<R>& k, R isi) {
     return k.a * rate_pow(-m_expm1(-k.b * isi), k.c);
+}
+
+// Surface fuel consumption (kg/m^2) of an unmixed fuel from FFMC and BUI
+// (M-1/M-2 mix the C-2 and D-1 values by percent conifer where they are
+// used; they get 0 here).
+template <typename R>
+__device__ R surface_consumption(int f, R ffmc, R bui) {
+    switch (f) {
+        case kC1:
+            return ffmc > (R)84 ? (R)0.75 + (R)0.75 * m_sqrt((R)1 - m_exp((R)-0.23 * (ffmc - (R)84)))
+                                : (R)0.75 - (R)0.75 * m_sqrt((R)1 - m_exp((R)-0.23 * ((R)84 - ffmc)));
+        case kC2:
+        case kM3:
+        case kM4: return (R)5 * ((R)1 - m_exp((R)-0.0115 * bui));
+        case kC3:
+        case kC4: return (R)5 * m_pow((R)1 - m_exp((R)-0.0164 * bui), (R)2.24);
+        case kC5:
+        case kC6: return (R)5 * m_pow((R)1 - m_exp((R)-0.0149 * bui), (R)2.48);
+        case kC7: {
+            const R ffc = ffmc > (R)70 ? (R)2 * ((R)1 - m_exp((R)-0.104 * (ffmc - (R)70))) : (R)0;
+            return ffc + (R)1.5 * ((R)1 - m_exp((R)-0.0201 * bui));
+        }
+        case kD1:
+        case kD2: return (R)1.5 * ((R)1 - m_exp((R)-0.0183 * bui));
+        case kS1: return (R)4 * ((R)1 - m_exp((R)-0.025 * bui)) + (R)4 * ((R)1 - m_exp((R)-0.034 * bui));
+        case kS2: return (R)10 * ((R)1 - m_exp((R)-0.013 * bui)) + (R)6 * ((R)1 - m_exp((R)-0.060 * bui));
+        case kS3: return (R)12 * ((R)1 - m_exp((R)-0.0166 * bui)) + (R)20 * ((R)1 - m_exp((R)-0.0210 * bui));
+        case kO1a:
+        case kO1b: return (R)kGrassFuelLoad;
+        default: return (R)0;
+    }
 }
 
 // Fill one table row from FFMC, BUI, wind speed (km/h) and the azimuth the
@@ -144,7 +176,9 @@ __device__ void weather_row(const CoefR<R>* coef, float ffmc_f, float bui_f, flo
             be = m_exp((R)50 * m_log(k.q) * ((R)1 / bui - (R)1 / k.bui0));
         row[kRowBE + f] = be;
         row[kRowG + f] = (k.a > (R)0) ? -m_expm1(-k.b * isz) : (R)0;
+        row[kRowSFC + f] = surface_consumption<R>(f, ffmc, bui);
     }
+    for (int k = kRowSFC + kNumFuels; k < kRowLen; ++k) row[k] = (R)0;
 }
 
 // ----------------------------------------------------------- cell rates
@@ -153,29 +187,39 @@ __device__ __forceinline__ uint32_t rec_nbmask(uint32_t info) { return (info >> 
 __device__ __forceinline__ int rec_gx(uint32_t g) { return (int)(int16_t)(g & 0xFFFFu); }
 __device__ __forceinline__ int rec_gn(uint32_t g) { return (int)(int16_t)(g >> 16); }
 
-// Landscape-wide constants of the mixed and grass fuels.
+// Landscape-wide constants of the mixed, grass and crowning fuels.
 template <typename R>
 struct LandR {
     R pc_w;    // percent conifer / 100 (M-1, M-2)
     R cf;      // grass curing factor (O-1a, O-1b)
     R cell_m;  // cell width, metres
+    R pdf_w;   // percent dead fir / 100 (M-3, M-4)
+    R fme_r;   // C-6 foliar moisture effect / its average 0.778
+    const R* csi;   // critical surface intensity for crowning per fuel, kW/m
 };
+
+__device__ __forceinline__ bool is_grass(int f) { return f == kO1a || f == kO1b; }
+__device__ __forceinline__ bool is_mix_pc(int f) { return f == kM1 || f == kM2; }
+__device__ __forceinline__ bool is_mix_pdf(int f) { return f == kM3 || f == kM4; }
 
 template <typename R>
 __device__ __forceinline__ R rsi_fuel(const CoefR<R>* coef, int f, R isi, const LandR<R>& L) {
-    // Mixedwood blends the C-2 and D-1 curves (M-2 takes 0.2 of D-1); every
-    // lane evaluates its own (or the C-2) curve, and the D-1 curve only runs
-    // when some lane of the wave is mixedwood.
-    const bool mixed = (f == kM1 || f == kM2);
-    R r = rsi_pure(coef[mixed ? (int)kC2 : f], isi);
+    // Mixedwoods blend a conifer curve with D-1: M-1/M-2 the C-2 curve by
+    // percent conifer, M-3/M-4 their dead-fir curve by percent dead fir
+    // (M-2 and M-4 take 0.2 of D-1).  Every lane evaluates its own (or the
+    // C-2) curve, and the D-1 curve only runs when some lane of the wave is
+    // a mixedwood.
+    const bool mix_pc = is_mix_pc(f), mixed = mix_pc || is_mix_pdf(f);
+    R r = rsi_pure(coef[mix_pc ? (int)kC2 : f], isi);
     if (__any(mixed)) {
         const R d1 = rsi_pure(coef[kD1], isi);
         if (mixed) {
-            const R wd1 = (f == kM2) ? (R)0.2 * ((R)1 - L.pc_w) : ((R)1 - L.pc_w);
-            r = L.pc_w * r + wd1 * d1;
+            const R w = mix_pc ? L.pc_w : L.pdf_w;
+            const R wd1 = (f == kM2 || f == kM4) ? (R)0.2 * ((R)1 - w) : ((R)1 - w);
+            r = w * r + wd1 * d1;
         }
     }
-    return (f >= kO1a) ? r * L.cf : r;
+    return is_grass(f) ? r * L.cf : r;
 }
 
 // Slope-equivalent wind speed (km/h).  The slope-adjusted zero-wind rate
@@ -196,12 +240,15 @@ __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, d
     const double ff = row[0], isz = row[1];
     // every lane inverts its own (or the C-2) curve; the D-1 curve only runs
     // when some lane of the wave is mixedwood
-    const bool mixed = (f == kM1 || f == kM2);
-    const int fa = mixed ? (int)kC2 : f;
+    const bool mix_pc = is_mix_pc(f), mixed = mix_pc || is_mix_pdf(f);
+    const int fa = mix_pc ? (int)kC2 : f;
     double isf = isf_curve(coef[fa], sfc, row[kRowG + fa]);
     if (__any(mixed)) {
         const double d1 = isf_curve(coef[kD1], sfd, row[kRowG + kD1]);
-        if (mixed) isf = L.pc_w * isf + (1.0 - L.pc_w) * d1;
+        if (mixed) {
+            const double w = mix_pc ? L.pc_w : L.pdf_w;
+            isf = w * isf + (1.0 - w) * d1;
+        }
     }
     double wse = ln_f64(isf * recip(isz)) * (1.0 / 0.05039);
     if (wse > 40.0) {
@@ -222,12 +269,15 @@ __device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float sfc, f
 
 __device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, float sfc, float sfd,
                                               const float* row, const LandR<float>& L) {
-    const bool mixed = (f == kM1 || f == kM2);
-    const int fa = mixed ? (int)kC2 : f;
+    const bool mix_pc = is_mix_pc(f), mixed = mix_pc || is_mix_pdf(f);
+    const int fa = mix_pc ? (int)kC2 : f;
     float isf = isf_curve32(coef[fa], sfc, row[kRowG + fa]);
     if (__any(mixed)) {
         const float d1 = isf_curve32(coef[kD1], sfd, row[kRowG + kD1]);
-        if (mixed) isf = L.pc_w * isf + (1.0f - L.pc_w) * d1;
+        if (mixed) {
+            const float w = mix_pc ? L.pc_w : L.pdf_w;
+            isf = w * isf + (1.0f - w) * d1;
+        }
     }
     return m_log(isf * recip(row[1])) * (1.0f / 0.05039f);
 }
@@ -237,7 +287,18 @@ __device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, f
 template <typename R>
 struct CellRates {
     R h, b, lb, lbm1, wx, wy, wsv;   // lbm1 = LB - 1, kept separately for accuracy
+    R rss;                           // C-6: its surface head rate; other fuels: h
 };
+
+// C-6 crown fire: the surface rate rss at spread index isi becomes rss +
+// CFB (RSC - rss), RSC = 60 (1 - exp(-0.0497 ISI)) FME / 0.778 and CFB =
+// 1 - exp(-0.23 (rss - RSO)) above the critical surface rate RSO = CSI /
+// (300 SFC), 0 below it.
+template <typename R>
+__device__ __forceinline__ R c6_rate(R rss, R isi, R rso, R fme_r) {
+    const R cfb = rss > rso ? -m_expm1((R)-0.23 * (rss - rso)) : (R)0;
+    return rss + cfb * ((R)60 * -m_expm1((R)-0.0497 * isi) * fme_r - rss);
+}
 
 // Everything is evaluated in R.  In FP32 the slope-equivalent wind switches
 // to FP64 from 39 km/h up: inverting the rate curve near its asymptote (the
@@ -269,11 +330,21 @@ __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const C
     const R be = row[kRowBE + f];
     const R isz = row[1];
     CellRates<R> out;
-    out.h = rsi_fuel(coef, f, isz * fw, L) * be;
-    out.b = rsi_fuel(coef, f, isz * recip(ew), L) * be;
+    const R isi_h = isz * fw, isi_b = isz * recip(ew);
+    out.h = rsi_fuel(coef, f, isi_h, L) * be;
+    out.b = rsi_fuel(coef, f, isi_b, L) * be;
+    out.rss = out.h;
+    if (__any(f == kC6)) {
+        if (f == kC6) {
+            const R sfc = row[kRowSFC + kC6];
+            const R rso = sfc > (R)0 ? L.csi[kC6] * recip((R)300 * sfc) : (R)3.0e38;
+            out.h = c6_rate<R>(out.rss, isi_h, rso, L.fme_r);
+            out.b = c6_rate<R>(out.b, isi_b, rso, L.fme_r);
+        }
+    }
     // LB - 1: grass 1.1 WSV^0.464 - 1 (0 below 1 km/h), other fuels
     // 8.729 (1 - exp(-0.030 WSV))^2.155, as one power per lane
-    const bool grass = f >= kO1a;
+    const bool grass = is_grass(f);
     const R lbase = grass ? wsv : -m_expm1((R)-0.030 * wsv);
     const R lpow = rate_pow(lbase, grass ? (R)0.464 : (R)2.155);
     out.lbm1 = grass ? ((wsv >= (R)1) ? (R)1.1 * lpow - (R)1 : (R)0) : (R)8.729 * lpow;
@@ -384,10 +455,33 @@ template <> __device__ __forceinline__ const CoefR<float>* coef_table<float>() {
 
 template <typename R> __device__ __forceinline__ LandR<R> land_consts(const LandDev* L);
 template <> __device__ __forceinline__ LandR<double> land_consts<double>(const LandDev* L) {
-    return LandR<double>{L->pc_w64, L->cf64, L->cell_m64};
+    return LandR<double>{L->pc_w64, L->cf64, L->cell_m64, L->pdf_w64, L->fme_r64, L->csi64};
 }
 template <> __device__ __forceinline__ LandR<float> land_consts<float>(const LandDev* L) {
-    return LandR<float>{L->pc_w32, L->cf32, L->cell_m32};
+    return LandR<float>{L->pc_w32, L->cf32, L->cell_m32, L->pdf_w32, L->fme_r32, L->csi32};
+}
+
+// Crown base height and crown fuel load per fuel.
+static __constant__ CrownCoef kCrown[kNumFuels] = {C2F_CROWN_ROWS};
+
+// Head fire intensity (kW/m) of a cell from its rates, before the noise
+// multiplier: 300 TFC ROS with TFC = SFC + CFL CFB, the crown fraction
+// burned CFB = 1 - exp(-0.23 (S - RSO)) above the critical surface rate RSO
+// = CSI / (300 SFC) (S the head rate, the surface rate for C-6; 0 for fuels
+// that do not crown).  *cfb (may be NULL) receives CFB.
+template <typename R>
+__device__ __forceinline__ R head_intensity(const CellRates<R>& cr, int f, const R* row, const LandR<R>& L,
+                                            R* cfb_out) {
+    R sfc = row[kRowSFC + f];
+    if (is_mix_pc(f)) sfc = L.pc_w * row[kRowSFC + kC2] + ((R)1 - L.pc_w) * row[kRowSFC + kD1];
+    const R cfl = (R)kCrown[f].cfl;
+    R cfb = (R)0;
+    if (cfl > (R)0 && sfc > (R)0) {
+        const R rso = L.csi[f] * recip((R)300 * sfc);
+        if (cr.rss > rso) cfb = -m_expm1((R)-0.23 * (cr.rss - rso));
+    }
+    if (cfb_out) *cfb_out = cfb;
+    return (R)300 * (sfc + cfb * cfl) * cr.h;
 }
 
 // Everything a rate evaluation needs besides the cell: coefficient tables,
@@ -405,6 +499,7 @@ struct RateCtx {
     int rounding;
     uint32_t rep;
     float burnout;   // burn-out threshold on the integer axis rates (0 = off)
+    float hfi_min;   // burn-out threshold on the head fire intensity, kW/m (0 = off)
 };
 
 // Weather scenario and ignition cell of replication `rep` of a job
@@ -468,7 +563,10 @@ __device__ __forceinline__ bool seeds_at(const Job& job, int p) {
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
 // the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.
 template <typename R>
-__device__ __forceinline__ void axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
+// Returns true when the cell burns out on its head fire intensity (A5 (iv)):
+// an intensity threshold is set and the intensity, with the noise
+// multiplier on the rate, is below it.
+__device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
                                        int32_t* q) {
     const size_t ro = (size_t)period * kRowLen;
     const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
@@ -479,6 +577,11 @@ __device__ __forceinline__ void axis_q(const RateCtx<R>& X, const CellRec& rec, 
         ub = draw(X.seed, cell, period, X.rep, 2u);
     }
     axis_rates_q<R>(cr, mu, X.rounding != 0, ua, ub, q);
+    if (X.hfi_min > 0.f) {
+        const R hfi = head_intensity<R>(cr, rec_fuel(rec.info), X.rows + ro, X.L, nullptr) * mu;
+        return !((double)hfi >= (double)X.hfi_min);
+    }
+    return false;
 }
 
 // Head rate times the noise multiplier: the receiving cell's ignition test.

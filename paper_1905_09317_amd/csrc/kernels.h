@@ -17,9 +17,11 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
 // from elev (NULL = flat) or, when grad_from is set, from the Horn
 // numerators of those records.
 hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, const CellRec* grad_from,
-                                    int rows, int cols, int cell_m, float pc, float curing, CellRec* recs,
-                                    int32_t* burnable, int32_t* tile_scratch, LandDev* land,
-                                    hipStream_t s);
+                                    int rows, int cols, int cell_m, float pc, float curing, float fmc,
+                                    float pdf, CellRec* recs, int32_t* burnable, int32_t* tile_scratch,
+                                    LandDev* land, hipStream_t s);
+// Rewrite the foliar-moisture and dead-fir constants of a landscape.
+hipError_t launch_fbp_consts(LandDev* land, float fmc, float pdf, hipStream_t s);
 
 // Scar comparison in one launch: out[t] = MSE, out[T + t] = SSIM of period
 // t, out[2T] = Frobenius norm of the last period's difference.  counts (3 T

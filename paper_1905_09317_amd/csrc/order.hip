@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void order_keys_kernel(const Job* __restrict__
     X.rounding = job.rounding;
     X.rep = rep;
     X.burnout = 0.f;
+    X.hfi_min = 0.f;
     const R h = head_rate<R>(X, rec, (uint32_t)ign, (uint32_t)p) * (R)job.period_min;
     // at most 2^20 m per period keeps the sum of up to 2^31 periods in 64 bits
     const unsigned long long v = (h > (R)0) ? (h < (R)1048576 ? (unsigned long long)h : 1048576ull) : 0ull;

@@ -82,8 +82,10 @@ __global__ void cellrec_kernel(const uint8_t* __restrict__ fuel, const int16_t* 
         if ((gx | gn) != 0 && f != kNonFuel) {
             // SF^(1/c) of the rate curve(s) the cell's slope effect uses
             const double sf = slope_factor(gx, gn, cell_m);
-            const bool mixed = (f == kM1 || f == kM2);
-            rec.sfc = pow(sf, 1.0 / kCoef64[mixed ? kC2 : f].c);
+            // mixedwoods: their conifer curve (C-2 for M-1/M-2, their own
+            // dead-fir curve for M-3/M-4) and the D-1 curve
+            const bool mix_pc = (f == kM1 || f == kM2), mixed = mix_pc || f == kM3 || f == kM4;
+            rec.sfc = pow(sf, 1.0 / kCoef64[mix_pc ? kC2 : f].c);
             if (mixed) rec.sfd = pow(sf, 1.0 / kCoef64[kD1].c);
         }
         recs[i] = rec;
@@ -187,7 +189,34 @@ __global__ void centre_kernel(const uint8_t* __restrict__ fuel, int rows, int co
 }
 
 // Landscape constants: M-1/M-2 conifer fraction and the O-1 curing factor
-// (0.005 (exp(0.061 C) - 1) below 58.8 % curing, 0.176 + 0.02 (C - 58.8) above).
+// (0.005 (exp(0.061 C) - 1) below 58.8 % curing, 0.176 + 0.02 (C - 58.8)
+// above); M-3/M-4 dead-fir fraction; from the foliar moisture content FMC the
+// C-6 moisture effect FME = 1000 (1.5 - 0.00275 FMC)^4 / (460 + 25.9 FMC)
+// over its average 0.778, and the critical surface intensity for crowning
+// 0.001 CBH^1.5 (460 + 25.9 FMC)^1.5 of every fuel.
+__global__ void fbpconst_kernel(LandDev* land, float fmc_f, float pdf_f) {
+    const int f = threadIdx.x;
+    const double fmc = (double)fmc_f;
+    const double h = pow(460.0 + 25.9 * fmc, 1.5);
+    if (f < kNumFuels) {
+        const double csi = 0.001 * pow(kCrown[f].cbh, 1.5) * h;
+        land->csi64[f] = csi;
+        land->csi32[f] = (float)csi;
+    }
+    if (f == 0) {
+        const double fme = 1000.0 * pow(1.5 - 0.00275 * fmc, 4.0) / (460.0 + 25.9 * fmc);
+        land->pdf_w64 = (double)pdf_f / 100.0;
+        land->fme_r64 = fme / 0.778;
+        land->pdf_w32 = pdf_f / 100.0f;
+        land->fme_r32 = (float)(fme / 0.778);
+    }
+}
+
+hipError_t launch_fbp_consts(LandDev* land, float fmc, float pdf, hipStream_t s) {
+    hipLaunchKernelGGL(fbpconst_kernel, dim3(1), dim3(64), 0, s, land, fmc, pdf);
+    return hipGetLastError();
+}
+
 __global__ void landconst_kernel(LandDev* land, float pc, float curing, int cell_m) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double c = (double)curing;
@@ -203,9 +232,9 @@ __global__ void landconst_kernel(LandDev* land, float pc, float curing, int cell
 }
 
 hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, const CellRec* grad_from,
-                                    int rows, int cols, int cell_m, float pc, float curing, CellRec* recs,
-                                    int32_t* burnable, int32_t* tile_scratch, LandDev* land,
-                                    hipStream_t s) {
+                                    int rows, int cols, int cell_m, float pc, float curing, float fmc,
+                                    float pdf, CellRec* recs, int32_t* burnable, int32_t* tile_scratch,
+                                    LandDev* land, hipStream_t s) {
     const int64_t n = (int64_t)rows * cols;
     const int g = fill_grid((size_t)n);
     hipError_t e;
@@ -220,6 +249,7 @@ hipError_t launch_prepare_landscape(const uint8_t* fuel, const int16_t* elev, co
     hipLaunchKernelGGL(burnable_scatter_kernel, dim3(n_tiles), dim3(kTileThreads), 0, s, fuel, n, tile_scratch, burnable);
     hipLaunchKernelGGL(centre_kernel, dim3(g), dim3(256), 0, s, fuel, rows, cols, land);
     hipLaunchKernelGGL(landconst_kernel, dim3(1), dim3(64), 0, s, land, pc, curing, cell_m);
+    hipLaunchKernelGGL(fbpconst_kernel, dim3(1), dim3(64), 0, s, land, fmc, pdf);
     return hipGetLastError();
 }
 
@@ -273,6 +303,8 @@ __global__ void eval_ros_kernel(EvalArgs a) {
     X.sigma = (R)a.sigma;
     X.rounding = a.rounding;
     X.rep = a.rep;
+    X.burnout = 0.f;
+    X.hfi_min = 0.f;
     const size_t ro = (size_t)a.period * kRowLen;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_cells; i += gridDim.x * blockDim.x) {
         const CellRec rec = a.cells[i];
@@ -283,6 +315,8 @@ __global__ void eval_ros_kernel(EvalArgs a) {
             if (a.fros) a.fros[i] = 0;
             if (a.lb) a.lb[i] = 0;
             if (a.raz) a.raz[i] = 0;
+            if (a.cfb) a.cfb[i] = 0;
+            if (a.hfi) a.hfi[i] = 0;
             for (int k = 0; k < 8; ++k) {
                 if (a.x8) a.x8[(size_t)i * 8 + k] = 0;
                 if (a.q8) a.q8[(size_t)i * 8 + k] = 0;
@@ -299,6 +333,12 @@ __global__ void eval_ros_kernel(EvalArgs a) {
         if (a.bros) a.bros[i] = (double)(cr.b * mu);
         if (a.fros) a.fros[i] = (double)((cr.h + cr.b) / ((R)2 * cr.lb) * mu);
         if (a.lb) a.lb[i] = (double)cr.lb;
+        if (a.cfb || a.hfi) {
+            R cfb = (R)0;
+            const R hfi = head_intensity<R>(cr, f, X.rows + ro, X.L, &cfb) * mu;
+            if (a.cfb) a.cfb[i] = (double)cfb;
+            if (a.hfi) a.hfi[i] = (double)hfi;
+        }
         if (a.raz) {
             double az = 0.0;
             if (cr.wsv > (R)0) {

@@ -109,8 +109,14 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
     int evals = 0;
     if (live != 0u && m0 <= e) {
         int32_t q[8];
-        axis_q<R>(X, rec, c, (uint32_t)p, q);
+        const bool faint = axis_q<R>(X, rec, c, (uint32_t)p, q);
         evals = 1;
+        if (faint) {
+            // burn-out (A5 (iv)): the head fire intensity is below the threshold
+#pragma unroll
+            for (int k = 0; k < 8; ++k) rem[k] = 0;
+            return evals;
+        }
         if (X.burnout > 0.f) {
             // burn-out (A5 (i)): every rate toward a burnable neighbour is
             // below delta, so the cell spreads no further
@@ -284,6 +290,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         X.rounding = job.rounding;
         X.rep = rep;
         X.burnout = job.burnout;
+        X.hfi_min = job.hfi_min;
 
         uint32_t c_entries = 0, c_conts = 0, c_evals = 0, c_cand = 0, c_impr = 0, c_ign = 0, c_rounds = 0;
         int max_list = 0;

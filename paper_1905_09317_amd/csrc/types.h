@@ -21,11 +21,14 @@ constexpr uint32_t kTagFresh = 4095u;                       // tag of a freshly 
 constexpr uint32_t kPlaneFill = 0xFFFFFFFFu;
 
 // Weather-table row: [0] f(F), [1] ISZ, [2] WS sin(WAZ), [3] WS cos(WAZ),
-// [4 + f] BUI effect of fuel f, [20 + f] 1 - exp(-b_f ISZ) of pure fuel f
-// (the zero-wind rate RSZ = a (1 - exp(-b ISZ))^c without its a and c).
-constexpr int kRowLen = 36;
+// [4 + f] BUI effect of fuel f, [23 + f] 1 - exp(-b_f ISZ) of pure fuel f
+// (the zero-wind rate RSZ = a (1 - exp(-b ISZ))^c without its a and c),
+// [42 + f] surface fuel consumption of fuel f (kg/m^2; M-1/M-2 mix the C-2
+// and D-1 entries by percent conifer where it is used).  19 fuel codes.
 constexpr int kRowBE = 4;
-constexpr int kRowG = 20;
+constexpr int kRowG = 23;
+constexpr int kRowSFC = 42;
+constexpr int kRowLen = 64;
 
 // Static per-cell record, 32 bytes:
 //   info: fuel code (bits 0-7) | mask of burnable neighbours (bits 8-15,
@@ -54,6 +57,14 @@ struct LandDev {
     unsigned long long centre_key;
     double pc_w64, cf64, cell_m64;
     float pc_w32, cf32, cell_m32, pad1;
+    // percent dead fir / 100 (M-3, M-4), and the C-6 foliar moisture effect
+    // relative to its average (FME / 0.778)
+    double pdf_w64, fme_r64;
+    float pdf_w32, fme_r32;
+    // critical surface intensity for crowning per fuel (kW/m):
+    // 0.001 CBH^1.5 (460 + 25.9 FMC)^1.5
+    double csi64[19];
+    float csi32[19];
 };
 
 // Entries of an ignition-point list carried by one request.
@@ -77,6 +88,7 @@ struct Job {
     uint64_t ign_total;
     int32_t burn_hours;        // daily burning window (0 = always)
     float burnout;             // burn-out rate threshold, m/min (0 = off)
+    float hfi_min;             // burn-out head fire intensity threshold, kW/m (0 = off)
     // ignition-point list (mode 4): (cell, period) pairs by period; each
     // cell is lit at minute period * period_min if it has not burned
     int32_t n_seeds;
@@ -162,6 +174,8 @@ struct EvalArgs {
     double* raz;
     double* x8;
     int32_t* q8;
+    double* cfb;
+    double* hfi;
 };
 
 }  // namespace c2f

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1905_09317_amd import _lib, fbp_coefficients
+from paper_1905_09317_amd import _lib, fbp_coefficients, fbp_crown_coefficients
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -33,8 +33,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    # 72 bytes up to burnout_ros, then n_ignitions, 4 bytes of padding and the list pointer
-    assert ctypes.sizeof(_lib.SimParams) == 4 * 4 + 8 + 4 * 2 + 4 * 9 + 4 + 4 + 4 + 8   # 88
+    # 72 bytes up to burnout_ros, then n_ignitions, 4 bytes of padding, the
+    # list pointer, hfi_min and 4 bytes of tail padding
+    assert ctypes.sizeof(_lib.SimParams) == 4 * 4 + 8 + 4 * 2 + 4 * 9 + 4 + 4 + 4 + 8 + 4 + 4   # 96
     assert ctypes.sizeof(_lib.Outputs) == 7 * 8 + 8
     assert ctypes.sizeof(_lib.WeatherRow) == 16
 
@@ -75,16 +76,17 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
             assert got[(pyname, fname)] == getattr(cls, fname).offset, (pyname, fname)
 
 
-@pytest.mark.parametrize("fuel", range(1, 16))
+@pytest.mark.parametrize("fuel", range(1, 19))
 def test_device_fuel_table_equals_oracle_table(fuel):
     assert np.array_equal(fbp_coefficients(fuel), oracle.fuel_coefficients(fuel))
+    assert np.array_equal(fbp_crown_coefficients(fuel), oracle.crown_coefficients(fuel))
 
 
 def test_bad_fuel_code_rejected():
     with pytest.raises(Exception):
         fbp_coefficients(0)
     with pytest.raises(Exception):
-        fbp_coefficients(16)
+        fbp_coefficients(19)
 
 
 def test_create_without_gpu_fails_cleanly():

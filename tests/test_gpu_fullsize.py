@@ -1,7 +1,8 @@
 """Parity at the full sizes of the measured workloads, in the launch
 configuration bench.py times: the whole single fire against the oracle, and
-sampled replications of the batched and large workloads (the oracle runs one
-replication at a time) plus properties that hold at any size."""
+the burn-count maps and every replication's area of the batched (2048
+replications) and large (64 replications) launches against the oracle run
+over all their replications, sharded over host processes."""
 import sys
 
 import numpy as np
@@ -9,7 +10,8 @@ import pytest
 
 from paper_1905_09317_amd import Request, Simulator, inputs
 
-from _helpers import assert_same_outputs, dilate, fp32_overrides, oracle_kwargs, oracle_run, request_kwargs
+from _helpers import (assert_same_outputs, dilate, fp32_overrides, oracle_kwargs, oracle_run, oracle_sharded,
+                      request_kwargs)
 
 pytestmark = pytest.mark.gpu
 
@@ -68,42 +70,29 @@ def test_single_fire_2048_fp32_full_with_audited_rates():
     assert_same_outputs(g, ref, SINGLE_OUTS, where="single fire fp32")
 
 
-def _sampled_mc(sim, w, sample):
+def _full_mc(sim, w):
+    """The workload's launch (as bench.py times it) against the oracle over
+    every replication: burn counts element by element and every area."""
     _, _, g = _run(sim, w, MC_OUTS)
-    burned = np.asarray(g["burned_cells"])
-    counts = np.asarray(g["burn_count"]).view(np.uint32)
-    # properties at full size
-    assert int(counts.sum(dtype=np.int64)) == int(burned.sum())
-    assert int(counts.max()) <= w.reps
-    assert (burned >= 1).all()          # every replication ignites a burnable cell
-    for r in sample:
-        _say(f"[fullsize] {w.name}: oracle replication {r}")
-        ref = oracle_run(w.fuel, w.elev, w.weather, want_rep_outputs=False,
-                         **oracle_kwargs(w, reps=1, rep_offset=r))
-        assert int(burned[r]) == int(ref["burned_cells"][0]), f"replication {r}"
-    return g
-
-
-def test_batched_mc_1024_2048reps_sampled(sim):
-    w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48)
-    g = _sampled_mc(sim, w, (0, 1, 777, 1500, 2047))
     st = sim.stats()
-    assert st["grid_blocks"] == 512 and st["relaunches"] == 0
-    # the burn-count map of a replication range equals the oracle's
-    ref = oracle_run(w.fuel, w.elev, w.weather, want_rep_outputs=False,
-                     **oracle_kwargs(w, reps=8, rep_offset=2040))
-    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m)
-    wx = sim.set_weather(w.weather)
-    part = sim.simulate(Request(landscape=land, weather=wx, outputs=MC_OUTS,
-                                **request_kwargs(w, reps=8, rep_offset=2040)))
-    assert_same_outputs(part, ref, MC_OUTS, where="reps 2040..2047")
-    assert np.array_equal(part["burned_cells"], np.asarray(g["burned_cells"])[2040:])
+    _say(f"[fullsize] {w.name}: oracle over all {w.reps} replications, sharded")
+    ref = oracle_sharded(w.fuel, w.elev, w.weather, w.reps,
+                         **{k: v for k, v in oracle_kwargs(w).items() if k != "reps"})
+    assert_same_outputs(g, ref, MC_OUTS, where=w.name)
+    assert (np.asarray(g["burned_cells"]) >= 1).all()   # every replication ignites a burnable cell
+    return g, st
 
 
-def test_large_8192_64reps_sampled(sim):
+def test_batched_mc_1024_2048reps_full(sim):
+    w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48)
+    _, st = _full_mc(sim, w)
+    assert st["grid_blocks"] == 512 and st["relaunches"] == 0 and st["rep_order"] == 1
+
+
+def test_large_8192_64reps_full(sim):
     w = inputs.large_landscape(side=8192, reps=64, n_periods=72)
-    _sampled_mc(sim, w, (0, 33, 63))
-    assert sim.stats()["grid_blocks"] == 64
+    _, st = _full_mc(sim, w)
+    assert st["grid_blocks"] == 64 and st["block_threads"] == 512
 
 
 def test_single_fire_2048_fp64_ignition_list_window_burnout():
@@ -195,36 +184,45 @@ def test_treatment_plans_1024_fused_sampled(sim):
     sim.unset_weather(wx)
 
 
-def test_batched_mc_1024_2048reps_fp32_audited_sampled(sim):
+def test_batched_mc_1024_2048reps_fp32_audited_in_launch(sim):
     """The batched workload with FP32 rates (2048 replications in one launch,
-    as `bench.py --workload batched --precision 1` times it).  Sampled
-    replications run again alone must give the same areas; their integer
-    rates are audited on every cell that burns in either precision and its
-    neighbours, and the audited boundary cases replayed into the oracle."""
+    as `bench.py --workload batched --precision 1` times it).  The launch
+    fuses two requests of the one landscape, replications 0..2039 and
+    2040..2047, the second returning its scars: 2048 work items in one
+    launch.  Every cell that burns in either precision, and
+    its neighbours, has its integer rates audited against the FP64 oracle
+    for every period; the audited boundary cases are replayed into the
+    oracle, which must then give the same scars and areas."""
     w = inputs.batched_monte_carlo(side=1024, reps=2048, n_scenarios=100, n_periods=48, precision=1)
     _say(f"[fullsize] {w.name} fp32")
-    land, wx, g = _run(sim, w, MC_OUTS + ("scenario",))
+    land = sim.load_landscape(w.fuel, w.elev, cell_m=w.cell_m, pc=w.pc, curing=w.curing)
+    wx = sim.set_weather(w.weather, period_min=w.period_min)
+    head = Request(landscape=land, weather=wx, outputs=MC_OUTS, **request_kwargs(w, reps=2040))
+    tail = Request(landscape=land, weather=wx, outputs=("scar", "burned_cells", "scenario", "burn_count"),
+                   **request_kwargs(w, reps=8, rep_offset=2040))
+    g0, g1 = sim.simulate_batch([head, tail])
     st = sim.stats()
-    assert st["relaunches"] == 0
-    burned = np.asarray(g["burned_cells"])
-    scen = np.asarray(g["scenario"])
-    counts = np.asarray(g["burn_count"]).view(np.uint32)
-    assert int(counts.sum(dtype=np.int64)) == int(burned.sum())
-    for r in (0, 1234, 2047):
-        alone = sim.simulate(Request(landscape=land, weather=wx, outputs=("scar", "burned_cells", "scenario"),
-                                     **request_kwargs(w, reps=1, rep_offset=r)))
-        assert int(alone["burned_cells"][0]) == int(burned[r]), f"replication {r} alone"
-        assert int(alone["scenario"][0]) == int(scen[r])
+    # one launch whose groups each run several replications, longest first
+    assert st["relaunches"] == 0 and st["grid_blocks"] < 2048 and st["rep_order"] == 1
+    burned = np.concatenate([np.asarray(g0["burned_cells"]), np.asarray(g1["burned_cells"])])
+    counts = np.asarray(g0["burn_count"]).view(np.uint32).astype(np.int64) + \
+        np.asarray(g1["burn_count"]).view(np.uint32)
+    assert int(counts.sum()) == int(burned.sum())
+    for k in (0, 4, 7):
+        r = 2040 + k
+        scen = int(np.asarray(g1["scenario"])[k])
         ref0 = oracle_run(w.fuel, w.elev, w.weather, **oracle_kwargs(w, reps=1, rep_offset=r))
-        burnt = (np.asarray(alone["scar"][0]) | ref0["scar"][0]).reshape(w.rows, w.cols).astype(bool)
+        assert scen == int(ref0["scenario"][0])
+        burnt = (np.asarray(g1["scar"][k]) | ref0["scar"][0]).reshape(w.rows, w.cols).astype(bool)
         cells = np.nonzero(dilate(burnt, 1).ravel())[0]
         _say(f"[fullsize] replication {r}: auditing {cells.size} cells x {w.n_periods} periods")
         keys, qs, n = fp32_overrides(sim, land, wx, w.fuel, w.elev, w.weather, reps=1, rep_ids=[r],
                                      n_periods=w.n_periods, seed=w.seed, sigma=w.sigma, rounding=w.rounding,
-                                     scenarios=[int(scen[r])], cells=cells)
+                                     scenarios=[scen], cells=cells)
         _say(f"[fullsize] replication {r}: {len(keys)} boundary cases in {n} audited integer rates")
         ref = oracle_run(w.fuel, w.elev, w.weather, overrides=(keys, qs),
                          **oracle_kwargs(w, reps=1, rep_offset=r))
-        assert_same_outputs(alone, ref, ("scar", "burned_cells", "scenario"), where=f"fp32 replication {r}")
+        got = {"scar": np.asarray(g1["scar"][k:k + 1]), "burned_cells": np.asarray(g1["burned_cells"][k:k + 1])}
+        assert_same_outputs(got, ref, ("scar", "burned_cells"), where=f"fp32 replication {r} in the launch")
     sim.unload_landscape(land)
     sim.unset_weather(wx)

@@ -57,7 +57,7 @@ def test_rate_field_parity(sim, precision, sigma, rounding):
     land = sim.load_landscape(fuel, elev, cell_m=100, pc=35.0, curing=70.0)
     w = sim.set_weather(wx)
     tol = 1e-5 if precision == 1 else 1e-11
-    qtol = 2e-5 if precision == 1 else 1e-12
+    qtol = 1e-5 if precision == 1 else 1e-12
     n_audit = 0
     for s in range(2):
         for p in range(6):
@@ -70,12 +70,14 @@ def test_rate_field_parity(sim, precision, sigma, rounding):
                 np.testing.assert_allclose(g[k], o[k], rtol=tol, atol=1e-9, err_msg=k)
             burn = fuel.ravel() != 0
             d = np.abs((g["raz"] - o["raz"] + 180.0) % 360.0 - 180.0)
-            # The spread azimuth is an angle of the effective wind vector; in
-            # FP32 its error grows as that vector shrinks by cancellation of
-            # wind against slope, where LB -> 1 and the direction stops
-            # mattering (the axis rates above carry the 1e-5 bar).
-            bar = 0.01 if precision else 1e-7
-            assert np.all(d[burn] <= bar), d.max()
+            # The spread azimuth is the angle of the effective wind vector:
+            # 1e-5 rad wherever the ellipse is elongated (LB > 1.001).  As the
+            # vector shrinks by cancellation of wind against slope, LB -> 1,
+            # the direction stops mattering and its FP32 angle loses digits;
+            # there the axis rates above carry the 1e-5 bar.
+            shaped = burn & (o["lb"] > 1.001)
+            assert np.all(np.radians(d[shaped]) <= (1e-5 if precision else 1e-9)), d[shaped].max()
+            assert np.all(d[burn] <= (0.01 if precision else 1e-7)), d[burn].max()
             np.testing.assert_allclose(g["x8"], o["x8"], rtol=tol, atol=1e-9)
             diff = g["q8"] != o["q8"]
             if diff.any():

@@ -123,7 +123,7 @@ def test_derive_checks_its_arguments(sim):
         sim.derive_landscape(base, [fuel.size], [0])
     assert e.value.status == -1
     with pytest.raises(C2FError) as e:
-        sim.derive_landscape(base, [0], [16])
+        sim.derive_landscape(base, [0], [19])   # codes run to 18 (M-4)
     assert e.value.status == -1
     with pytest.raises(C2FError) as e:
         sim.derive_landscape(base + 1000, [0], [0])
