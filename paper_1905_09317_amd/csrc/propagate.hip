@@ -215,7 +215,10 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             s_item = it;
         }
         __syncthreads();
-        const int item = s_item;
+        // values every thread reads from LDS after a barrier are the same in
+        // every lane: readfirstlane tells the compiler so, which keeps the
+        // job record and everything derived from it in scalar registers
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= total_items) break;
 
         // job lookup (jobs are sorted by item_base)
@@ -276,15 +279,16 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             }
         }
         __syncthreads();
-        const uint32_t tag = s_tag;
+        const uint32_t tag = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_tag);
+        const int scen_r = __builtin_amdgcn_readfirstlane(s_scen);
         const uint32_t pendv = (tag << kMinuteBits) | kPendingMinute;
         RateCtx<R> X;
         X.coef = s_coef;
         X.coef64 = s_coef64;
         X.L = land_consts<R>(job.land);
         X.L64 = land_consts<double>(job.land);
-        X.rows = (const R*)job.table + (size_t)s_scen * job.n_wp * kRowLen;
-        X.rows64 = job.table64 + (size_t)s_scen * job.n_wp * kRowLen;
+        X.rows = (const R*)job.table + (size_t)scen_r * job.n_wp * kRowLen;
+        X.rows64 = job.table64 + (size_t)scen_r * job.n_wp * kRowLen;
         X.seed = job.seed;
         X.sigma = (R)job.sigma;
         X.rounding = job.rounding;
