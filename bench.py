@@ -46,9 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # roofline.traffic only while the sources are unchanged.
 KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
-    "single-fire-2048x2048-48h": ("a6732ed5dd7111bb", 10_373_633),
-    "batched-mc-1024x1024-2048reps": ("a6732ed5dd7111bb", 40_930_828_329),
-    "large-8192x8192-64reps-72h": ("a6732ed5dd7111bb", 795_486_998),
+    "single-fire-2048x2048-48h": ("8b8919c8fd30a3f1", 10_482_425),
+    "batched-mc-1024x1024-2048reps": ("8b8919c8fd30a3f1", 44_256_794_214),
+    "large-8192x8192-64reps-72h": ("8b8919c8fd30a3f1", 815_608_440),
 }
 
 
