@@ -191,6 +191,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
 
     const int tid = threadIdx.x;
     const int slot = blockIdx.x;
+    __builtin_amdgcn_s_setprio(1);
     if (tid < kNumFuels) {
         s_coef[tid] = coef_table<R>()[tid];
         s_coef64[tid] = coef_table<double>()[tid];
@@ -549,10 +550,13 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             }
             if (__lane_id() == 0) atomicAdd(&s_hb, ~0ull);   // no longer a holder
 
-            // label correcting over the period's queue
+            // label correcting over the period's queue.  A wave waiting for
+            // entries drops to the lowest issue priority, so that its polling
+            // takes no issue slots from the waves working on the chain.
             for (;;) {
                 int base = 0, cnt = 0;
                 bool done = false;
+                __builtin_amdgcn_s_setprio(0);
                 if (__lane_id() == 0) {
                     for (;;) {
                         if (__hip_atomic_load(&s_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
@@ -587,6 +591,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                 base = lane_value(base, 0);
                 cnt = lane_value(cnt, 0);
                 done = lane_value((int)done, 0) != 0;
+                __builtin_amdgcn_s_setprio(1);
                 if (done) break;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 ++c_rounds;
