@@ -476,6 +476,8 @@ def main():
                     help="also time this many replications one per launch (default: 64 for "
                          "multi-replication workloads, 0 = off)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tuning", default="",
+                    help="tuning cache file: loaded when it exists; written after --autotune")
     ap.add_argument("--rep-order", type=int, default=1, choices=[0, 1],
                     help="1: groups running several replications take the longest predicted "
                          "first (default); 0: index order")
@@ -527,8 +529,12 @@ def main():
                   ignition_cell=w.ignition_cell, scenario_mode=w.scenario_mode,
                   scenario=w.scenario, outputs=dense_outputs(w), device_out=True)
     sim.set_rep_order(args.rep_order)
+    if args.tuning and os.path.exists(args.tuning):
+        sim.load_tuning(args.tuning)
     if args.autotune:
         sim.autotune(req)
+        if args.tuning:
+            sim.save_tuning(args.tuning)
     if args.block:
         sim.set_tuning(args.block, 0)
 

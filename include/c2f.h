@@ -52,7 +52,8 @@ typedef enum {
     C2F_EDEVICE = -3,   /* HIP runtime error or no suitable device */
     C2F_ECAPACITY = -4, /* work lists overflowed even at the largest capacity */
     C2F_ESTATE = -5,    /* unknown landscape/weather id or ticket, or wrong call order */
-    C2F_EBUSY = -6      /* serving queue is full */
+    C2F_EBUSY = -6,     /* serving queue is full */
+    C2F_EIO = -7        /* a file could not be opened, read or written */
 } c2f_status;
 
 typedef struct c2f_ctx c2f_ctx;
@@ -338,6 +339,23 @@ c2f_status c2f_set_rep_order(c2f_ctx* ctx, int32_t mode);
  * timing candidates on the device; the choice is kept for requests of the
  * same grid size and replication count. */
 c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* representative);
+
+/* Tuning cache on disk, so that a choice made by c2f_autotune (or a list
+ * capacity raised after an overflow) carries over to later contexts and
+ * processes.  c2f_save_tuning writes every entry the context holds to the
+ * text file `path` (replaced whole); c2f_load_tuning reads such a file and
+ * adds its entries to the context (an entry for the same grid size,
+ * replication count and precision replaces the context's).  The file names
+ * the device it was tuned on (architecture and compute-unit count) and one
+ * entry per line:
+ *   c2f-tuning 1 <arch> <compute units>
+ *   <cells> <replications> <precision> <block threads> <list capacity>
+ * Loading a file tuned on another kind of device, or a malformed file,
+ * fails with C2F_EINVAL and changes nothing; a missing file is C2F_EIO.
+ * Block sizes must be one of 64, 128, 256, 512, 768, 1024 and list
+ * capacities 1 .. 2^30. */
+c2f_status c2f_save_tuning(c2f_ctx* ctx, const char* path);
+c2f_status c2f_load_tuning(c2f_ctx* ctx, const char* path);
 
 /* Counters of the most recent simulate/simulate_batch call. */
 typedef struct {

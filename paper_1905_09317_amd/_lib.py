@@ -8,9 +8,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libc2f.so")
 
-C2F_OK, C2F_EINVAL, C2F_ENOMEM, C2F_EDEVICE, C2F_ECAPACITY, C2F_ESTATE, C2F_EBUSY = 0, -1, -2, -3, -4, -5, -6
+C2F_OK, C2F_EINVAL, C2F_ENOMEM, C2F_EDEVICE, C2F_ECAPACITY, C2F_ESTATE, C2F_EBUSY, C2F_EIO = (
+    0, -1, -2, -3, -4, -5, -6, -7)
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ECAPACITY", -5: "ESTATE",
-                -6: "EBUSY"}
+                -6: "EBUSY", -7: "EIO"}
 
 
 class WeatherRow(ctypes.Structure):
@@ -95,6 +96,8 @@ def load() -> ctypes.CDLL:
         "c2f_set_landscape_fbp": ([P, i32, f32, f32], i32),
         "c2f_set_tuning": ([P, i32, i64], i32),
         "c2f_autotune": ([P, pp(SimParams)], i32),
+        "c2f_save_tuning": ([P, ctypes.c_char_p], i32),
+        "c2f_load_tuning": ([P, ctypes.c_char_p], i32),
         "c2f_get_stats": ([P, pp(RunStats)], i32),
         "c2f_submit": ([P, pp(SimParams), pp(Outputs), pp(u64)], i32),
         "c2f_poll": ([P, u64, pp(i32)], i32),
@@ -120,7 +123,7 @@ DECLARED = ("c2f_create", "c2f_destroy", "c2f_last_error", "c2f_set_stream", "c2
             "c2f_unload_landscape", "c2f_set_weather", "c2f_unset_weather", "c2f_simulate",
             "c2f_simulate_batch", "c2f_simulate_noalloc", "c2f_count_work", "c2f_eval_ros", "c2f_fbp_coefficients", "c2f_fbp_crown_coefficients",
             "c2f_set_landscape_fbp", "c2f_set_tuning",
-            "c2f_autotune", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
+            "c2f_autotune", "c2f_save_tuning", "c2f_load_tuning", "c2f_get_stats", "c2f_submit", "c2f_poll", "c2f_wait",
             "c2f_wait_info", "c2f_set_serving", "c2f_get_memory", "c2f_set_rep_order",
             "c2f_set_ignition_map", "c2f_derive_landscape", "c2f_compare_scars",
             "c2f_compare_scars_async")

@@ -6,6 +6,7 @@ numpy arrays and torch tensors to the C ABI of include/c2f.h and back.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -337,6 +338,15 @@ class Simulator:
         req = req or Request(**kw)
         p = req.params()
         self._check(self._L.c2f_autotune(self._ctx, ctypes.byref(p)))
+
+    def save_tuning(self, path: str):
+        """Write the context's tuning entries (block size and list capacity
+        per grid size, replication count and precision) to a text file."""
+        self._check(self._L.c2f_save_tuning(self._ctx, os.fsencode(path)))
+
+    def load_tuning(self, path: str):
+        """Add the entries of a tuning file written on the same kind of device."""
+        self._check(self._L.c2f_load_tuning(self._ctx, os.fsencode(path)))
 
     def stats(self) -> dict:
         s = RunStats()

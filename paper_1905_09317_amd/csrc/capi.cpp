@@ -169,6 +169,7 @@ struct c2f_ctx {
     size_t lane_plane_budget = 0;   // plane pool of one serving lane
     size_t lane_list_budget = 0;    // list pool of one serving lane
     int n_cu = 0;
+    std::string arch;           // device architecture, e.g. "gfx950" (feature suffixes dropped)
     std::chrono::steady_clock::time_point t0;
     void* scratch = nullptr;    // device address of the no-allocation scratch on `device`
     void* acct = nullptr;       // work counts: 3 counters and a job record (allocated on first use)
@@ -1366,6 +1367,7 @@ c2f_status c2f_create(int32_t device, uint64_t hbm_budget_bytes, c2f_ctx** out) 
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return C2F_EDEVICE;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return C2F_EDEVICE;
     ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch.assign(prop.gcnArchName, strcspn(prop.gcnArchName, ": \t\n"));
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return C2F_EDEVICE;
     ctx->admit_limit = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
@@ -2159,6 +2161,85 @@ c2f_status c2f_autotune(c2f_ctx* ctx, const c2f_sim_params* rep) {
     if (st != C2F_OK) return st;
     std::lock_guard<std::mutex> lk2(ctx->tunemu);
     ctx->tune[TuneKey{n, rep->reps, rep->precision}] = TuneVal{best_block, cap};
+    return C2F_OK;
+}
+
+c2f_status c2f_save_tuning(c2f_ctx* ctx, const char* path) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (!path || !*path) return fail(ctx, C2F_EINVAL, "no path");
+    std::map<TuneKey, TuneVal> tune;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tunemu);
+        tune = ctx->tune;
+    }
+    // written next to the target and renamed over it, so that a reader
+    // never sees a half-written file
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(ctx, C2F_EIO, "cannot write %s", tmp.c_str());
+    bool ok = std::fprintf(f, "c2f-tuning 1 %s %d\n", ctx->arch.c_str(), ctx->n_cu) > 0;
+    for (const auto& kv : tune)
+        ok = ok && std::fprintf(f, "%lld %d %d %d %lld\n", (long long)kv.first.cells, kv.first.reps,
+                                kv.first.precision, kv.second.block, (long long)kv.second.list_cap) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(ctx, C2F_EIO, "cannot write %s", path);
+    }
+    return C2F_OK;
+}
+
+c2f_status c2f_load_tuning(c2f_ctx* ctx, const char* path) {
+    if (!ctx) return C2F_EINVAL;
+    ApiScope api(ctx);
+    if (!path || !*path) return fail(ctx, C2F_EINVAL, "no path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(ctx, C2F_EIO, "cannot read %s", path);
+    std::map<TuneKey, TuneVal> got;
+    char line[512];
+    int lineno = 0;
+    c2f_status st = C2F_OK;
+    while (st == C2F_OK && std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (!std::strchr(line, '\n') && !std::feof(f)) {
+            st = fail(ctx, C2F_EINVAL, "%s:%d: line too long", path, lineno);
+            break;
+        }
+        int used = 0;
+        if (lineno == 1) {
+            char arch[64];
+            int version = 0, n_cu = 0;
+            if (std::sscanf(line, "c2f-tuning %d %63s %d %n", &version, arch, &n_cu, &used) != 3 ||
+                line[used] != '\0' || version != 1)
+                st = fail(ctx, C2F_EINVAL, "%s: not a tuning file of version 1", path);
+            else if (ctx->arch != arch || n_cu != ctx->n_cu)
+                st = fail(ctx, C2F_EINVAL, "%s: tuned on %s with %d compute units, this device is %s with %d", path,
+                          arch, n_cu, ctx->arch.c_str(), ctx->n_cu);
+            continue;
+        }
+        long long cells = 0, cap = 0;
+        int reps = 0, precision = 0, block = 0;
+        if (std::sscanf(line, "%lld %d %d %d %lld %n", &cells, &reps, &precision, &block, &cap, &used) != 5 ||
+            line[used] != '\0') {
+            st = fail(ctx, C2F_EINVAL, "%s:%d: expected <cells> <reps> <precision> <block> <capacity>", path, lineno);
+            break;
+        }
+        const bool block_ok = block == 64 || block == 128 || block == 256 || block == 512 || block == 768 ||
+                              block == 1024;
+        if (cells < 1 || reps < 1 || precision < 0 || precision > 1 || !block_ok || cap < 1 || cap > (1LL << 30)) {
+            st = fail(ctx, C2F_EINVAL, "%s:%d: value out of range", path, lineno);
+            break;
+        }
+        got[TuneKey{(int64_t)cells, reps, precision}] = TuneVal{block, (int64_t)cap};
+    }
+    const bool read_error = std::ferror(f) != 0;
+    std::fclose(f);
+    if (st != C2F_OK) return st;
+    if (read_error) return fail(ctx, C2F_EIO, "cannot read %s", path);
+    if (lineno == 0) return fail(ctx, C2F_EINVAL, "%s: empty file", path);
+    std::lock_guard<std::mutex> lk(ctx->tunemu);
+    for (const auto& kv : got) ctx->tune[kv.first] = kv.second;
     return C2F_OK;
 }
 
