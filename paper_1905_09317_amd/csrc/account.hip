@@ -32,11 +32,13 @@ __global__ __launch_bounds__(256) void work_counts_kernel(const Job* __restrict_
                                                           unsigned long long* __restrict__ out) {
     __shared__ CoefR<R> s_coef[kNumFuels];
     __shared__ CoefR<double> s_coef64[kNumFuels];
+    __shared__ CoefR<float> s_coef32[kNumFuels];
     __shared__ unsigned long long s_sum[3];
     const int tid = threadIdx.x;
     if (tid < kNumFuels) {
         s_coef[tid] = coef_table<R>()[tid];
         s_coef64[tid] = coef_table<double>()[tid];
+        s_coef32[tid] = coef_table<float>()[tid];
     }
     if (tid < 3) s_sum[tid] = 0ull;
     __syncthreads();
@@ -79,6 +81,9 @@ __global__ __launch_bounds__(256) void work_counts_kernel(const Job* __restrict_
         X.L64 = land_consts<double>(job.land);
         X.rows = (const R*)job.table + (size_t)scen * job.n_wp * kRowLen;
         X.rows64 = job.table64 + (size_t)scen * job.n_wp * kRowLen;
+        X.coef32 = s_coef32;
+        X.L32 = land_consts<float>(job.land);
+        X.rows32 = job.table32 ? job.table32 + (size_t)scen * job.n_wp * kRowLen : nullptr;
         X.seed = job.seed;
         X.sigma = (R)job.sigma;
         X.rounding = job.rounding;

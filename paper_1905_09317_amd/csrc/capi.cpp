@@ -756,6 +756,7 @@ Job make_job(const c2f_sim_params& p, const Landscape& L, const Weather& W, cons
     j.land = L.land;
     j.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
     j.table64 = W.t64;
+    j.table32 = W.t32;
     j.rows = L.rows;
     j.cols = L.cols;
     j.d_orth = L.cell_m;
@@ -2006,6 +2007,7 @@ c2f_status c2f_eval_ros(c2f_ctx* ctx, int32_t landscape_id, int32_t weather_id, 
     a.land = L.land;
     a.table = precision == 1 ? (const void*)W.t32 : (const void*)W.t64;
     a.table64 = W.t64;
+    a.table32 = W.t32;
     a.n_cells = (int32_t)n;
     a.scenario = scenario;
     a.period = period;

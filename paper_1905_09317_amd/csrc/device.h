@@ -500,6 +500,12 @@ struct RateCtx {
     uint32_t rep;
     float burnout;   // burn-out threshold on the integer axis rates (0 = off)
     float hfi_min;   // burn-out threshold on the head fire intensity, kW/m (0 = off)
+    // FP32 coefficient table, landscape constants and weather rows of the
+    // same scenario: an FP64 context tries them first (axis_q).  rows32
+    // NULL: FP64 only.
+    const CoefR<float>* coef32;
+    LandR<float> L32;
+    const float* rows32;
 };
 
 // Weather scenario and ignition cell of replication `rep` of a job
@@ -562,12 +568,12 @@ __device__ __forceinline__ bool seeds_at(const Job& job, int p) {
 
 // Integer axis rates (m/min) of a cell in a period: eq. (1) rates scaled by
 // the noise multiplier, then floor(x + u) with u = 1/2 or a Philox uniform.
-template <typename R>
 // Returns true when the cell burns out on its head fire intensity (A5 (iv)):
 // an intensity threshold is set and the intensity, with the noise
 // multiplier on the rate, is below it.
-__device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
-                                       int32_t* q) {
+template <typename R>
+__device__ __forceinline__ bool axis_q_direct(const RateCtx<R>& X, const CellRec& rec, uint32_t cell,
+                                              uint32_t period, int32_t* q) {
     const size_t ro = (size_t)period * kRowLen;
     const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
     const R mu = noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
@@ -582,6 +588,61 @@ __device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, 
         return !((double)hfi >= (double)X.hfi_min);
     }
     return false;
+}
+
+// Integer rates of an FP64 context from an FP32 evaluation where that is
+// exact.  The FP32 rates differ from the FP64 ones by at most 7.0e-6 of
+// max(1, x) over 630 M axis rates of the 1024^2 batched landscape (its 16
+// fuel codes, sloped ground, 10 scenarios x 8 periods, noise, stochastic
+// rounding), and head fire intensities by at most 1.2e-5 relative.  So
+// where x32 + u lies more than kMixMargin max(1, x32) from an integer,
+// floor(x64 + u) is the same integer, and where the FP32 intensity lies
+// more than kMixMarginH of the threshold from it, the burn-out test agrees.
+// Lanes where either test fails take the FP64 evaluation.  The margins leave a factor of about
+// three over the measured differences; every FP64 parity test compares the
+// result with the FP64 oracle bit for bit.
+constexpr double kMixMargin = 2e-5;
+constexpr double kMixMarginH = 5e-5;
+
+template <typename R>
+__device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
+                                       int32_t* q) {
+    if constexpr (sizeof(R) == 8) {
+        if (X.rows32 != nullptr) {
+            const size_t ro = (size_t)period * kRowLen;
+            const CellRates<float> cr =
+                cell_rates<float>(X.coef32, X.coef64, rec, X.rows32 + ro, X.rows64 + ro, X.L32, X.L64);
+            const float mu = noise_mult<float>(X.seed, cell, period, X.rep, (float)X.sigma);
+            uint4 ua = make_uint4(0u, 0u, 0u, 0u), ub = ua;
+            if (X.rounding != 0) {
+                ua = draw(X.seed, cell, period, X.rep, 1u);
+                ub = draw(X.seed, cell, period, X.rep, 2u);
+            }
+            float x[8];
+            axis_rates<float>(cr, mu, x);
+            const uint32_t w[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
+            bool exact = true;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double u = X.rounding != 0 ? unit24<double>(w[k]) : 0.5;
+                const double v = (double)x[k] + u;
+                const double m = kMixMargin * fmax(1.0, (double)x[k]);
+                const double lo = floor(v - m);
+                exact = exact && lo == floor(v + m);
+                q[k] = (lo < 1073741824.0) ? (int32_t)lo : 1073741824;
+            }
+            bool faint = false;
+            if (X.hfi_min > 0.f) {
+                const double hfi =
+                    (double)(head_intensity<float>(cr, rec_fuel(rec.info), X.rows32 + ro, X.L32, nullptr) * mu);
+                const double hm = (double)X.hfi_min;
+                exact = exact && fabs(hfi - hm) > kMixMarginH * hm;
+                faint = !(hfi >= hm);
+            }
+            if (exact) return faint;
+        }
+    }
+    return axis_q_direct<R>(X, rec, cell, period, q);
 }
 
 // Head rate times the noise multiplier: the receiving cell's ignition test.

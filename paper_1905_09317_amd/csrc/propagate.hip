@@ -188,6 +188,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     __shared__ unsigned long long s_cnt[kNumCounters];
     __shared__ CoefR<R> s_coef[kNumFuels];
     __shared__ CoefR<double> s_coef64[kNumFuels];
+    __shared__ CoefR<float> s_coef32[kNumFuels];
 
     const int tid = threadIdx.x;
     const int slot = blockIdx.x;
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     if (tid < kNumFuels) {
         s_coef[tid] = coef_table<R>()[tid];
         s_coef64[tid] = coef_table<double>()[tid];
+        s_coef32[tid] = coef_table<float>()[tid];
     }
     uint32_t* __restrict__ plane = slots.planes + (size_t)slot * (size_t)slots.plane_cells;
     const int64_t stride = slots.list_cap;   // entries allocated per list
@@ -290,6 +292,9 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         X.L64 = land_consts<double>(job.land);
         X.rows = (const R*)job.table + (size_t)scen_r * job.n_wp * kRowLen;
         X.rows64 = job.table64 + (size_t)scen_r * job.n_wp * kRowLen;
+        X.coef32 = s_coef32;
+        X.L32 = land_consts<float>(job.land);
+        X.rows32 = job.table32 ? job.table32 + (size_t)scen_r * job.n_wp * kRowLen : nullptr;
         X.seed = job.seed;
         X.sigma = (R)job.sigma;
         X.rounding = job.rounding;

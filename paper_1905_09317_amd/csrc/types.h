@@ -77,6 +77,7 @@ struct Job {
     const LandDev* land;
     const void* table;         // [n_scen][n_wp][kRowLen] weather terms, double or float
     const double* table64;     // the same terms in FP64 (slope-equivalent wind)
+    const float* table32;      // the same terms in FP32 (an FP64 job tries them first); may be NULL
     int32_t rows, cols, d_orth, d_diag;
     int32_t n_scen, n_wp, period_min, n_periods;
     int32_t T, reps, rep_offset, item_base;
@@ -162,6 +163,7 @@ struct EvalArgs {
     const LandDev* land;
     const void* table;
     const double* table64;
+    const float* table32;
     int32_t n_cells, scenario, period, n_wp;
     uint32_t rep;
     int32_t rounding;
