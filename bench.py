@@ -255,12 +255,13 @@ def served_bench(args) -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ["f64", "f32"][st.precision],
+        "dtype": ["f32+f64", "f32"][st.precision],
         "data": "synthetic",
         "config": {"workload": st.name, "queries": len(st.queries), "rate_per_s": args.rate,
                    "side": [128, 4096], "reps": [1, 256], "n_periods": st.n_periods,
                    "lanes": args.lanes, "ros_sigma": st.sigma, "rounding": "stochastic",
-                   "rate_precision": ["fp64", "fp32"][st.precision], "ignition": "uniform-burnable"},
+                   "rate_precision": ["fp64 results (fp32 first, fp64 near rounding boundaries)", "fp32"][st.precision],
+                   "ignition": "uniform-burnable"},
         "latency_ms": {"p50": s["latency_ms_p50"], "p99": s["latency_ms_p99"],
                        "mean": s["latency_ms_mean"], "max": s["latency_ms_max"]},
         "queue_ms": {"p50": s["queue_ms_p50"], "p99": s["queue_ms_p99"]},
@@ -351,7 +352,7 @@ def treatment_bench(args) -> None:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"treatments-{n_plans}plans-{w.rows}x{w.cols}-{reps}reps", "plans": n_plans,
                    "reps_per_plan": reps, "n_periods": w.n_periods, "scenarios": int(w.weather.shape[0]),
@@ -583,13 +584,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if w.precision == 1 else "f64",
+        # precision 0: FP32 evaluation, FP64 where a rounding decision is close
+        "dtype": "f32" if w.precision == 1 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "rows": w.rows, "cols": w.cols, "cell_m": w.cell_m,
                    "reps": w.reps, "n_periods": w.n_periods, "period_min": w.period_min,
                    "scenarios": int(w.weather.shape[0]), "ros_sigma": w.sigma,
                    "rounding": ["nearest", "stochastic"][w.rounding],
-                   "rate_precision": ["fp64", "fp32"][w.precision],
+                   "rate_precision": ["fp64 results (fp32 first, fp64 near rounding boundaries)",
+                                      "fp32"][w.precision],
                    "ignition": ["fixed", "uniform-burnable", "nearest-centre"][w.ignition_mode],
                    "block_threads": st["block_threads"], "grid_blocks": st["grid_blocks"],
                    "rep_order": st["rep_order"],

@@ -175,7 +175,12 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *                  ignites at the start of the first later period that passes.
  *   rounding       axis rates are integer m/min: 0 = floor(x + 1/2),
  *                  1 = floor(x + u) with u uniform from Philox.
- *   precision      0 = FBP evaluated in FP64, 1 = in FP32.
+ *   precision      0 = FP64 results: the integer rates (and the intensity
+ *                  burn-out test) are those of an FP64 evaluation.  Each
+ *                  cell is evaluated in FP32 first; where x + u lies
+ *                  within 2e-5 max(1, x) of an integer (or the intensity
+ *                  within 5e-5 of its threshold), the FP64 evaluation
+ *                  decides.  1 = FP32 rates throughout.
  *   ignition_mode  0 = ignition_cell, 1 = uniform over burnable cells,
  *                  2 = the burnable cell nearest (rows/2, cols/2),
  *                  3 = drawn from the landscape's ignition map
