@@ -178,9 +178,11 @@ c2f_status c2f_unset_weather(c2f_ctx* ctx, int32_t weather_id);
  *   precision      0 = FP64 results: the integer rates (and the intensity
  *                  burn-out test) are those of an FP64 evaluation.  Each
  *                  cell is evaluated in FP32 first; where x + u lies
- *                  within 2e-5 max(1, x) of an integer (or the intensity
- *                  within 5e-5 of its threshold), the FP64 evaluation
- *                  decides.  1 = FP32 rates throughout.
+ *                  within 3e-5 max(1, x) of an integer, the intensity
+ *                  within 2e-4 of its threshold, or the wind speed within
+ *                  1e-3 km/h of a switch of the model's form (40 km/h,
+ *                  and 1 km/h for grass), the FP64 evaluation decides.
+ *                  1 = FP32 rates throughout.
  *   ignition_mode  0 = ignition_cell, 1 = uniform over burnable cells,
  *                  2 = the burnable cell nearest (rows/2, cols/2),
  *                  3 = drawn from the landscape's ignition map

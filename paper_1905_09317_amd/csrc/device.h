@@ -261,22 +261,30 @@ __device__ __forceinline__ double slope_wind(const CoefR<double>* coef, int f, d
 // taken with log1p accuracy (log_1m), so a gentle slope (x close to the zero-slope value)
 // keeps full relative precision in ISF, and WSE = ln(ISF / ISZ) / 0.05039
 // then carries an absolute error of a few 1e-6 km/h.  Near and above the
-// 40 km/h branch point the caller switches to slope_wind in FP64.
-__device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float sfc, float g) {
-    const float x = sfc * g;
+// 40 km/h branch point the caller switches to slope_wind in FP64, and so it
+// does where ill is set: x = SF^(1/c) (1 - exp(-b ISZ)) above 0.8, where
+// ln(1 - x) multiplies the relative error of x by x / (1 - x) and the 0.01
+// floor of the curve is near (steep slopes in fast fuels).
+constexpr float kIllX = 0.8f;
+
+__device__ __forceinline__ float isf_curve32(const CoefR<float>& k, float x) {
     return -log_1m(x > 0.99f ? 0.99f : x) * recip(k.b);
 }
 
 __device__ __forceinline__ float slope_wind32(const CoefR<float>* coef, int f, float sfc, float sfd,
-                                              const float* row, const LandR<float>& L) {
+                                              const float* row, const LandR<float>& L, bool& ill) {
     const bool mix_pc = is_mix_pc(f), mixed = mix_pc || is_mix_pdf(f);
     const int fa = mix_pc ? (int)kC2 : f;
-    float isf = isf_curve32(coef[fa], sfc, row[kRowG + fa]);
+    const float xo = sfc * row[kRowG + fa];
+    float isf = isf_curve32(coef[fa], xo);
+    ill = xo > kIllX;
     if (__any(mixed)) {
-        const float d1 = isf_curve32(coef[kD1], sfd, row[kRowG + kD1]);
+        const float xd = sfd * row[kRowG + kD1];
+        const float d1 = isf_curve32(coef[kD1], xd);
         if (mixed) {
             const float w = mix_pc ? L.pc_w : L.pdf_w;
             isf = w * isf + (1.0f - w) * d1;
+            ill = ill || xd > kIllX;
         }
     }
     return m_log(isf * recip(row[1])) * (1.0f / 0.05039f);
@@ -288,7 +296,13 @@ template <typename R>
 struct CellRates {
     R h, b, lb, lbm1, wx, wy, wsv;   // lbm1 = LB - 1, kept separately for accuracy
     R rss;                           // C-6: its surface head rate; other fuels: h
+    // WSV lies within kEdgeWsv km/h of a speed where the model switches
+    // form and its value jumps: f(W) at 40 km/h, grass LB at 1 km/h.  An
+    // FP32 evaluation there may take the other branch than FP64.
+    bool edge;
 };
+
+constexpr float kEdgeWsv = 1e-3f;
 
 // C-6 crown fire: the surface rate rss at spread index isi becomes rss +
 // CFB (RSC - rss), RSC = 60 (1 - exp(-0.0497 ISI)) FME / 0.778 and CFB =
@@ -303,6 +317,8 @@ __device__ __forceinline__ R c6_rate(R rss, R isi, R rso, R fme_r) {
 // Everything is evaluated in R.  In FP32 the slope-equivalent wind switches
 // to FP64 from 39 km/h up: inverting the rate curve near its asymptote (the
 // WSE > 40 branch) turns a relative error of 1e-7 in ISF into ~1e-4 in WSE.
+// It does so too where the inversion's argument is ill-conditioned
+// (slope_wind32's ill).
 // row64 is the FP64 weather row of the same (scenario, period).
 template <typename R>
 __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const CoefR<double>* coef64,
@@ -314,8 +330,9 @@ __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const C
         R wse = (R)0;
         bool need64 = true;
         if constexpr (sizeof(R) == 4) {
-            wse = slope_wind32(coef, f, (float)rec.sfc, (float)rec.sfd, row, L);
-            need64 = !(wse < 39.0f);
+            bool ill;
+            wse = slope_wind32(coef, f, (float)rec.sfc, (float)rec.sfd, row, L, ill);
+            need64 = ill || !(wse < 39.0f);
         }
         if (need64) wse = (R)slope_wind(coef64, f, rec.sfc, rec.sfd, row64, L64);
         const R ig = recip(m_sqrt((R)gx * (R)gx + (R)gn * (R)gn));
@@ -352,6 +369,7 @@ __device__ __forceinline__ CellRates<R> cell_rates(const CoefR<R>* coef, const C
     out.wx = wx;
     out.wy = wy;
     out.wsv = wsv;
+    out.edge = fabs((double)wsv - 40.0) < (double)kEdgeWsv || (grass && fabs((double)wsv - 1.0) < (double)kEdgeWsv);
     return out;
 }
 
@@ -591,18 +609,22 @@ __device__ __forceinline__ bool axis_q_direct(const RateCtx<R>& X, const CellRec
 }
 
 // Integer rates of an FP64 context from an FP32 evaluation where that is
-// exact.  The FP32 rates differ from the FP64 ones by at most 7.0e-6 of
-// max(1, x) over 630 M axis rates of the 1024^2 batched landscape (its 16
-// fuel codes, sloped ground, 10 scenarios x 8 periods, noise, stochastic
-// rounding), and head fire intensities by at most 1.2e-5 relative.  So
-// where x32 + u lies more than kMixMargin max(1, x32) from an integer,
-// floor(x64 + u) is the same integer, and where the FP32 intensity lies
-// more than kMixMarginH of the threshold from it, the burn-out test agrees.
-// Lanes where either test fails take the FP64 evaluation.  The margins leave a factor of about
-// three over the measured differences; every FP64 parity test compares the
-// result with the FP64 oracle bit for bit.
-constexpr double kMixMargin = 2e-5;
-constexpr double kMixMarginH = 5e-5;
+// exact.  Away from the speeds where the model's form jumps (f(W) at 40
+// km/h, grass LB at 1 km/h), FP32 axis rates differ from the FP64 ones by
+// at most 7.0e-6 of max(1, x) over 630 M rates of the 1024^2 batched
+// landscape (its 16 fuel codes, 10 scenarios x 8 periods, noise, stochastic
+// rounding) and 9.4e-6 over 5 harsh landscapes (all 18 fuels, slopes above
+// 100 %, FFMC 80-99, BUI up to 250, winds up to 80 km/h), and head fire
+// intensities by at most 4.5e-5 relative.  So where x32 + u lies more than
+// kMixMargin max(1, x32) from an integer, floor(x64 + u) is the same
+// integer, and where the FP32 intensity lies more than kMixMarginH of the
+// threshold from it, the burn-out test agrees.  A cell whose FP32 wind
+// speed lies within kEdgeWsv of a jump (CellRates::edge), and every lane
+// where either test fails, takes the FP64 evaluation.  The margins leave a
+// factor of three or more over the measured differences; every FP64 parity
+// test compares the result with the FP64 oracle bit for bit.
+constexpr double kMixMargin = 3e-5;
+constexpr double kMixMarginH = 2e-4;
 
 template <typename R>
 __device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period,
@@ -621,7 +643,7 @@ __device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, 
             float x[8];
             axis_rates<float>(cr, mu, x);
             const uint32_t w[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
-            bool exact = true;
+            bool exact = !cr.edge;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const double u = X.rounding != 0 ? unit24<double>(w[k]) : 0.5;
