@@ -122,3 +122,36 @@ def test_stochastic_rounding_on_steep_ground_matches_the_oracle(sim):
         assert np.array_equal(g["q8"], o["q8"]), p
     sim.unload_landscape(land)
     sim.unset_weather(w)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_settings_match_the_oracle(sim, seed):
+    """Random grids, slopes, landscape settings and weather (including calm,
+    40 km/h and storm winds), noise and stochastic rounding: the integer
+    rates of precision 0 equal the oracle's."""
+    rng = np.random.default_rng(900 + seed)
+    rows, cols = int(rng.integers(24, 72)), int(rng.integers(24, 72))
+    fuel = rng.integers(1, 19, (rows, cols)).astype(np.uint8)
+    elev = inputs.elevation_grid(rows, cols, 950 + seed, elev_max=float(rng.choice([0.0, 400.0, 2500.0, 6000.0])))
+    cell_m = int(rng.choice([25, 50, 100, 250]))
+    pc, curing = float(rng.uniform(0, 100)), float(rng.uniform(0, 100))
+    fmc, pdf = float(rng.uniform(80, 130)), float(rng.uniform(0, 100))
+    land = sim.load_landscape(fuel, elev, cell_m=cell_m, pc=pc, curing=curing)
+    sim.set_landscape_fbp(land, fmc=fmc, pdf=pdf)
+    n_p = 6
+    wx = np.zeros((1, n_p, 4), np.float32)
+    wx[0, :, 0] = rng.uniform(70, 99, n_p)
+    wx[0, :, 1] = rng.uniform(0, 300, n_p)
+    wx[0, :, 2] = rng.choice([0.0, 1.0, 5.0, 39.99, 40.0, 40.01, 60.0, 120.0], n_p)
+    wx[0, :, 3] = rng.uniform(0, 360, n_p)
+    w = sim.set_weather(wx)
+    sigma = float(np.float32(rng.choice([0.0, 0.15, 0.4])))
+    rounding = int(rng.integers(0, 2))
+    _say(f"mixed precision: random settings seed {seed} {rows}x{cols} cell {cell_m}")
+    for p in range(n_p):
+        g = sim.eval_ros(land, w, period=p, rep=seed, seed=77 + seed, sigma=sigma, rounding=rounding, precision=0)
+        o = oracle.eval_ros(fuel, elev, wx, period=p, rep=seed, seed=77 + seed, sigma=sigma, rounding=rounding,
+                            cell_m=cell_m, pc=pc, curing=curing, fmc=fmc, pdf=pdf)
+        assert np.array_equal(g["q8"], o["q8"]), (p, int((g["q8"] != o["q8"]).sum()))
+    sim.unload_landscape(land)
+    sim.unset_weather(w)
