@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void work_counts_kernel(const Job* __restrict_
         X.L64 = land_consts<double>(job.land);
         X.rows = (const R*)job.table + (size_t)scen * job.n_wp * kRowLen;
         X.rows64 = job.table64 + (size_t)scen * job.n_wp * kRowLen;
+        X.row_stride = kRowLen;
         X.coef32 = s_coef32;
         X.L32 = land_consts<float>(job.land);
         X.rows32 = job.table32 ? job.table32 + (size_t)scen * job.n_wp * kRowLen : nullptr;

@@ -512,6 +512,9 @@ struct RateCtx {
     LandR<double> L64;
     const R* rows;          // first row of the replication's scenario
     const double* rows64;
+    // elements from one period's row to the next: kRowLen, or 0 where
+    // rows, rows64 and rows32 hold only the period being evaluated
+    uint32_t row_stride;
     uint64_t seed;
     R sigma;
     int rounding;
@@ -592,7 +595,7 @@ __device__ __forceinline__ bool seeds_at(const Job& job, int p) {
 template <typename R>
 __device__ __forceinline__ bool axis_q_direct(const RateCtx<R>& X, const CellRec& rec, uint32_t cell,
                                               uint32_t period, int32_t* q) {
-    const size_t ro = (size_t)period * kRowLen;
+    const size_t ro = (size_t)period * X.row_stride;
     const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
     const R mu = noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
     uint4 ua = make_uint4(0u, 0u, 0u, 0u), ub = ua;
@@ -631,7 +634,7 @@ __device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, 
                                        int32_t* q) {
     if constexpr (sizeof(R) == 8) {
         if (X.rows32 != nullptr) {
-            const size_t ro = (size_t)period * kRowLen;
+            const size_t ro = (size_t)period * X.row_stride;
             const CellRates<float> cr =
                 cell_rates<float>(X.coef32, X.coef64, rec, X.rows32 + ro, X.rows64 + ro, X.L32, X.L64);
             const float mu = noise_mult<float>(X.seed, cell, period, X.rep, (float)X.sigma);
@@ -670,7 +673,7 @@ __device__ __forceinline__ bool axis_q(const RateCtx<R>& X, const CellRec& rec, 
 // Head rate times the noise multiplier: the receiving cell's ignition test.
 template <typename R>
 __device__ __forceinline__ R head_rate(const RateCtx<R>& X, const CellRec& rec, uint32_t cell, uint32_t period) {
-    const size_t ro = (size_t)period * kRowLen;
+    const size_t ro = (size_t)period * X.row_stride;
     const CellRates<R> cr = cell_rates<R>(X.coef, X.coef64, rec, X.rows + ro, X.rows64 + ro, X.L, X.L64);
     return cr.h * noise_mult<R>(X.seed, cell, period, X.rep, X.sigma);
 }

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) void order_keys_kernel(const Job* __restrict__
     X.L64 = land_consts<double>(job.land);
     X.rows = (const R*)job.table + (size_t)scen * job.n_wp * kRowLen;
     X.rows64 = job.table64 + (size_t)scen * job.n_wp * kRowLen;
+    X.row_stride = kRowLen;
     X.coef32 = coef_table<float>();
     X.L32 = land_consts<float>(job.land);
     X.rows32 = job.table32 ? job.table32 + (size_t)scen * job.n_wp * kRowLen : nullptr;

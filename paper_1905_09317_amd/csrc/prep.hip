@@ -299,6 +299,7 @@ __global__ void eval_ros_kernel(EvalArgs a) {
     X.L64 = land_consts<double>(a.land);
     X.rows = (const R*)a.table + (size_t)a.scenario * a.n_wp * kRowLen;
     X.rows64 = a.table64 + (size_t)a.scenario * a.n_wp * kRowLen;
+    X.row_stride = kRowLen;
     X.coef32 = coef_table<float>();
     X.L32 = land_consts<float>(a.land);
     X.rows32 = a.table32 ? a.table32 + (size_t)a.scenario * a.n_wp * kRowLen : nullptr;

@@ -189,6 +189,14 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
     __shared__ CoefR<R> s_coef[kNumFuels];
     __shared__ CoefR<double> s_coef64[kNumFuels];
     __shared__ CoefR<float> s_coef32[kNumFuels];
+    // the weather rows of the period being propagated (FP64, and FP32 where
+    // the context evaluates in FP32 or tries FP32 first), staged at the
+    // start of each period so that every evaluation reads them from LDS
+    __shared__ double s_row64[kRowLen];
+    __shared__ float s_row32[kRowLen];
+    // the landscape's critical surface intensities, per fuel
+    __shared__ double s_csi64[kNumFuels];
+    __shared__ float s_csi32[kNumFuels];
 
     const int tid = threadIdx.x;
     const int slot = blockIdx.x;
@@ -246,6 +254,10 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         const uint32_t last_cell = (uint32_t)((int64_t)rows * cols - 1);
 
         // ------------------------------------------- replication set-up
+        if (tid < kNumFuels) {
+            s_csi64[tid] = job.land->csi64[tid];
+            s_csi32[tid] = job.land->csi32[tid];
+        }
         if (tid == 0) {
             const uint32_t prev = slots.tags[slot];
             s_refill = prev <= 1u;   // tags exhausted: refill this slot's plane
@@ -290,11 +302,21 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
         X.coef64 = s_coef64;
         X.L = land_consts<R>(job.land);
         X.L64 = land_consts<double>(job.land);
-        X.rows = (const R*)job.table + (size_t)scen_r * job.n_wp * kRowLen;
-        X.rows64 = job.table64 + (size_t)scen_r * job.n_wp * kRowLen;
+        if constexpr (sizeof(R) == 8) X.L.csi = (const R*)s_csi64;
+        else X.L.csi = (const R*)s_csi32;
+        X.L64.csi = s_csi64;
+        const size_t so = (size_t)scen_r * job.n_wp * kRowLen;
+        const double* const g_rows64 = job.table64 + so;
+        const float* const g_rows32 =
+            sizeof(R) == 4 ? (const float*)job.table + so : (job.table32 ? job.table32 + so : nullptr);
+        if constexpr (sizeof(R) == 8) X.rows = (const R*)s_row64;
+        else X.rows = (const R*)s_row32;
+        X.rows64 = s_row64;
+        X.row_stride = 0;
         X.coef32 = s_coef32;
         X.L32 = land_consts<float>(job.land);
-        X.rows32 = job.table32 ? job.table32 + (size_t)scen_r * job.n_wp * kRowLen : nullptr;
+        X.L32.csi = s_csi32;
+        X.rows32 = g_rows32 ? s_row32 : nullptr;
         X.seed = job.seed;
         X.sigma = (R)job.sigma;
         X.rounding = job.rounding;
@@ -368,6 +390,12 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
             // outside the daily burning window nothing spreads or ignites:
             // the continuations and pending cells wait, unchanged
             if (!burning_period(job, p)) continue;
+            // every wave has left the previous period (its end barriers)
+            for (int i = tid; i < kRowLen; i += BLOCK) {
+                s_row64[i] = g_rows64[(size_t)p * kRowLen + i];
+                if (g_rows32) s_row32[i] = g_rows32[(size_t)p * kRowLen + i];
+            }
+            __syncthreads();
             const int32_t s = p * P + 1;   // first minute of period p
             const int32_t e = (p + 1) * P; // last minute of period p
 
