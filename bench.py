@@ -46,9 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # roofline.traffic only while the sources are unchanged.
 KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
-    "single-fire-2048x2048-48h": ("ba94fadacf80ac40", 10_570_428),
-    "batched-mc-1024x1024-2048reps": ("ba94fadacf80ac40", 44_745_084_267),
-    "large-8192x8192-64reps-72h": ("ba94fadacf80ac40", 825_475_519),
+    "single-fire-2048x2048-48h": ("72188c56d5f0c0e3", 10_568_991),
+    "batched-mc-1024x1024-2048reps": ("72188c56d5f0c0e3", 46_236_832_009),
+    "large-8192x8192-64reps-72h": ("72188c56d5f0c0e3", 825_924_574),
 }
 
 

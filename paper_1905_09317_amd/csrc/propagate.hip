@@ -558,7 +558,11 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                 append_g(keep, ct, gC[cc ^ 1], cap, &s_nC[cc ^ 1], &s_flag);
             };
 
-            // continuations of p-1, advanced from the start of p
+            // Continuations of p-1, advanced from the start of p, last
+            // listed first: the cells listed last were lit latest in p-1, at
+            // the front of the fire, and tend to start the longest chains of
+            // p, which then reach the queue in the first rounds.  Labels are
+            // a least fixed point whatever the order.
             {
                 const int n = (int)min((int64_t)s_nC[cc], cap);
                 if (n > max_list) max_list = n;
@@ -568,7 +572,7 @@ __global__ __launch_bounds__(BLOCK, 2) void propagate_kernel(const Job* __restri
                     uint32_t c = 0, lab = 0;
                     int32_t rem[8];
                     if (act) {
-                        const Cont ct = gC[cc][i];
+                        const Cont ct = gC[cc][n - 1 - i];
                         c = ct.c;
                         lab = ct.label;
 #pragma unroll
