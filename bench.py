@@ -46,9 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # roofline.traffic only while the sources are unchanged.
 KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
-    "single-fire-2048x2048-48h": ("72188c56d5f0c0e3", 10_568_991),
-    "batched-mc-1024x1024-2048reps": ("72188c56d5f0c0e3", 46_236_832_009),
-    "large-8192x8192-64reps-72h": ("72188c56d5f0c0e3", 825_924_574),
+    "single-fire-2048x2048-48h": ("96f8bad8dbf652f9", 10_503_435),
+    "batched-mc-1024x1024-2048reps": ("96f8bad8dbf652f9", 46_238_681_485),
+    "large-8192x8192-64reps-72h": ("96f8bad8dbf652f9", 825_783_656),
 }
 
 

@@ -76,6 +76,18 @@ __device__ __forceinline__ void append_g(bool pred, const T& val, T* glob, int64
 }
 
 
+// ceil(r / q) for 0 < q < r < 2^16.  The float quotient x = r rcp(q) (rcp
+// within one ulp) differs from r / q by less than (r / q) 2^-22, which is
+// below 1 / q because r < 2^22.  With r / q = k + f: for f = 0, x lies in
+// (k - 1, k + 1) and truncates to k - 1 or k; for f >= 1 / q, x lies in
+// (k, k + 1) and truncates to k.  One exact 24-bit product then takes the
+// truncation up to ceil(r / q) where it is one short.
+__device__ __forceinline__ int32_t ceil_div_small(int32_t r, int32_t q) {
+    uint32_t t = (uint32_t)((float)r * __builtin_amdgcn_rcpf((float)q));
+    t += __umul24(t, (uint32_t)q) < (uint32_t)r;
+    return (int32_t)t;
+}
+
 // Advance cell c (label lab) through period p from minute m0 to e.  nbv[k]
 // is the label of neighbour k read at the start of the pass; rem[k] holds
 // the metres left on axis k (0 = done).  On return cand[k] is the
@@ -144,12 +156,13 @@ __device__ __forceinline__ int advance(const RateCtx<R>& X, const CellRec& rec, 
                 if (qk >= r || n >= r) {
                     reach = true;
                 } else {
-                    step = qk * n;
+                    // qk < r < 2^16 and n < r: a 24-bit product
+                    step = (int32_t)__umul24((uint32_t)qk, (uint32_t)n);
                     reach = step >= r;
                 }
             }
             if (reach) {
-                cand[k] = m0 + (r + qk - 1) / qk - 1;
+                cand[k] = m0 + (qk >= r ? 1 : ceil_div_small(r, qk)) - 1;
                 rem[k] = 0;
             } else {
                 rem[k] = r - step;
