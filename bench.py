@@ -46,9 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # roofline.traffic only while the sources are unchanged.
 KERNEL_SOURCES = ("propagate.hip", "device.h", "ln64.h", "types.h", "fuel_table.h")
 TRAFFIC = {
-    "single-fire-2048x2048-48h": ("96f8bad8dbf652f9", 10_503_435),
-    "batched-mc-1024x1024-2048reps": ("96f8bad8dbf652f9", 46_238_681_485),
-    "large-8192x8192-64reps-72h": ("96f8bad8dbf652f9", 825_783_656),
+    "single-fire-2048x2048-48h": ("688daae243f8835b", 10_503_435),
+    "batched-mc-1024x1024-2048reps": ("688daae243f8835b", 46_238_681_485),
+    "large-8192x8192-64reps-72h": ("688daae243f8835b", 825_783_656),
 }
 
 

@@ -18,9 +18,10 @@
 //   - cells waiting for a passing rate (pending) are re-tested;
 //   - cells whose axes were still travelling at the end of p-1
 //     (continuations, with the metres left on each axis) are advanced
-//     through p;
+//     through p, those listed last (lit latest, at the fire front) first;
 //   - label correcting: each cell that received a smaller arrival in p is
 //     advanced from that minute to the end of p.
+// The period's weather rows and the coefficient tables are read from LDS.
 // Advancing a cell through a period costs one FBP evaluation; axes that
 // reach their neighbour inside p offer that minute with atomicMin on the
 // neighbour's 32-bit label, the rest become a continuation for p+1.
